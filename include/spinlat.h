@@ -1,0 +1,179 @@
+/*
+ * spinlat.h -- C ABI of the MI355X (gfx950) checkerboard Metropolis library.
+ *
+ * The library runs the sub-lattice-parallel ("checkerboard") Metropolis sweep
+ * of "Simulating lattice spin models on GPUs" (Levy, Cohen & Rabani,
+ * arXiv:1209.0296):
+ *   - Ising model, Sec. 3 Eq. 1-2 with the reading H = -J sum_<ij> s_i s_j
+ *     - h sum_i s_i over forward nearest-neighbour bonds of a periodic
+ *     L^2 or L^3 lattice, spin-1/2 (s = +-1) or spin-1 (s in {-1,0,+1});
+ *   - North-East facilitated model, Sec. 3.2 Eq. 3 with J = 0: occupation
+ *     n in {0,1}, a site may change only when its north and east neighbours
+ *     are up; equilibrium up-density c;
+ *   - Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.1), evaluated as an
+ *     integer compare of a 32-bit Philox4x32-10 word against a threshold
+ *     table computed on the host in double precision;
+ *   - one sweep = colour 0 (sites with (x+y[+z]) even) then colour 1
+ *     (Alg. I steps 5-7, Fig. 3: two non-interacting sub-lattices).
+ *
+ * Random-number contract (result is a pure function of seed, sweep and site,
+ * so any launch schedule gives the same lattice bit for bit):
+ *   word(seed, tag, t, colour, k, w, j) =
+ *     Philox4x32-10(key = (seed mod 2^32, seed >> 32),
+ *                   ctr = (k / G, colour, t, tag))[(k mod G)*w + j],  G = 4/w,
+ *   w = 1 (spin-1/2, NE) or 2 (spin-1); tag 0 = sweep, 1 = initial state;
+ *   k = (natural row-major site index) >> 1 (L even).
+ *   Spin-1/2: accept s -> -s iff word < thr.  Spin-1: word j=0 accepts,
+ *   word j=1 picks the proposal (lower of the two other values iff < 2^31).
+ *   NE: word decides up-flips (thr = floor(min(1, c/(1-c)) 2^32)) and
+ *   down-flips (floor(min(1, (1-c)/c) 2^32)).
+ *   Initial state: word(seed, 1, 0, colour, k, 1, 0): spin-1/2 +1 iff
+ *   < 2^31; spin-1 floor(3 word / 2^32) - 1; NE up iff < floor(c 2^32).
+ *   Threshold: thr(dE) = 2^32 if dE <= 0, else floor(exp(-dE/T) 2^32), with
+ *   dE = -(double)(s'-s) * (J * (double)nsum + h) and nsum the sum of the
+ *   2*dim neighbours.
+ *
+ * Records: record r_0 describes the state at creation; r_{i+1} the state after
+ * sweep t0+i: {t, bond_sum = sum_i sum_{d<dim} s_i s_{i+e_d}, mag = sum_i s_i
+ * (NE: sum_i n_i, bond_sum over n), accepted = moves accepted in that sweep,
+ * unflipped = NE sites not flipped since the persistence origin (-1 for
+ * Ising)}.  Energy: Ising E = -J bond_sum - h mag.
+ *
+ * Ownership: the caller owns the device buffer (sl_query_bytes bytes, 256-byte
+ * aligned) and the HIP stream; the handle borrows both and must be destroyed
+ * before either goes away.  All device work is enqueued on that stream.
+ * Errors: every function returns a status; nothing is thrown across the ABI;
+ * sl_last_error() gives a thread-local message for the last failure.
+ * Thread safety: one handle must not be used from two threads at once.
+ */
+#ifndef SPINLAT_H
+#define SPINLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SL_ABI_VERSION 1u
+
+typedef struct sl_lattice sl_lattice; /* opaque, owned by the library */
+
+typedef enum sl_status {
+    SL_OK = 0,
+    SL_E_INVALID = 1,     /* a parameter is out of its domain */
+    SL_E_UNSUPPORTED = 2, /* valid model, but no kernel for it (e.g. L % 8 != 0) */
+    SL_E_BUFFER = 3,      /* caller buffer too small, misaligned or NULL */
+    SL_E_HIP = 4,         /* a HIP runtime call failed (message has its text) */
+    SL_E_STATE = 5,       /* call not allowed now (record ring full, ...) */
+    SL_E_OVERFLOW = 6     /* sweep index would reach 2^32 */
+} sl_status;
+
+typedef enum sl_model { SL_ISING = 0, SL_NORTH_EAST = 1 } sl_model;
+
+typedef enum sl_init {
+    SL_INIT_COLD = 0,   /* Ising: every spin +1 */
+    SL_INIT_RANDOM = 1, /* Ising: uniform over the spin values; NE: up w.p. c */
+    SL_INIT_BUFFER = 2  /* copy init_spins (device, natural order) */
+} sl_init;
+
+typedef struct sl_params {
+    uint32_t abi_version;     /* must be SL_ABI_VERSION */
+    int32_t model;            /* sl_model; NE requires dim == 2 and two_s == 1 */
+    int32_t dim;              /* 2 or 3 */
+    int32_t L;                /* linear size, even, >= 2; kernels need L % 8 == 0 */
+    int32_t two_s;            /* 1: s in {-1,+1}; 2: s in {-1,0,+1} */
+    int32_t init;             /* sl_init */
+    double J, h, T;           /* Ising coupling, field, temperature (T > 0, may be +inf) */
+    double c;                 /* NE up-density, 0 < c < 1 */
+    uint64_t seed;            /* Philox key */
+    uint64_t t0;              /* index of the first sweep (resume), < 2^32 */
+    uint64_t record_capacity; /* records held on the device between sl_measure calls, >= 1 */
+    const int8_t* init_spins; /* SL_INIT_BUFFER: device pointer to L^dim bytes in natural
+                                 row-major order [z][y][x] (Ising: s; NE: n | flag<<1) */
+} sl_params;
+
+typedef struct sl_record {
+    uint64_t t;
+    int64_t bond_sum;
+    int64_t mag;
+    int64_t accepted;
+    int64_t unflipped;
+} sl_record;
+
+/* Launch schedule.  Every schedule produces the same lattice and records. */
+typedef enum sl_mode {
+    SL_MODE_AUTO = 0,   /* library's choice for the shape */
+    SL_MODE_SIMPLE = 1, /* one thread per 4 same-colour sites, direct global loads,
+                           two launches per sweep */
+    SL_MODE_HALF = 2,   /* LDS tile + halo per workgroup, two launches per sweep */
+    SL_MODE_FUSED = 3   /* LDS tile with a 2-deep halo: both colours in one launch,
+                           colour-0 halo updates recomputed (2D only) */
+} sl_mode;
+
+typedef struct sl_launch {
+    int32_t mode;        /* sl_mode */
+    int32_t tile_rows;   /* LDS modes: rows of the tile (2D: y; 3D: y and z each) */
+    int32_t tile_words;  /* LDS modes: 4-byte words of one colour row per tile */
+    int32_t reserved;
+} sl_launch;
+
+/* Bytes of device memory the lattice needs (spins, record ring, tables).
+ * Host-only, pure.  SL_E_INVALID / SL_E_UNSUPPORTED as sl_create_lattice. */
+sl_status sl_query_bytes(const sl_params* params, size_t* device_bytes);
+
+/* Threshold table the kernels use (host-only, pure).  Ising: 4*(4*dim+1)
+ * entries, [di][nsum + 2*dim] for s'-s = {-2,-1,+1,+2}[di]; NE: {up, down}.
+ * Each entry is in [0, 2^32]. */
+sl_status sl_threshold_table(const sl_params* params, uint64_t* out, size_t cap,
+                             size_t* n_out);
+
+/* Bind the caller's device buffer and stream, initialise the lattice and
+ * record r_0.  Work is enqueued on the stream; the call does not synchronise.
+ * hip_stream is a hipStream_t (NULL: the default stream). */
+sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t bytes,
+                            void* hip_stream, sl_lattice** out);
+
+/* Choose the launch schedule for later sweeps (validated; SL_E_UNSUPPORTED if
+ * the schedule does not fit the shape). */
+sl_status sl_set_launch(sl_lattice* lat, const sl_launch* launch);
+sl_status sl_get_launch(const sl_lattice* lat, sl_launch* launch);
+
+/* Enqueue n sweeps (Monte Carlo steps) on the stream; asynchronous.  Fails
+ * with SL_E_STATE (nothing enqueued) if the unread records would exceed
+ * record_capacity, SL_E_OVERFLOW if the sweep index would reach 2^32. */
+sl_status sl_sweep(sl_lattice* lat, uint64_t n);
+
+/* Synchronise the stream and move all unread records to out[0..n) (host
+ * memory).  SL_E_BUFFER (nothing drained) if cap is smaller than the count. */
+sl_status sl_measure(sl_lattice* lat, sl_record* out, size_t cap, size_t* n_out);
+
+/* Number of unread records and the index of the next sweep. */
+sl_status sl_status_counts(const sl_lattice* lat, uint64_t* pending, uint64_t* next_t);
+
+/* Enqueue a copy of the lattice into device_out (L^dim bytes, natural
+ * row-major order, NE bytes include the flag bit).  Asynchronous. */
+sl_status sl_copy_spins(sl_lattice* lat, int8_t* device_out, size_t n);
+
+/* NE: clear every "has flipped" flag; the persistence origin becomes the
+ * current sweep.  Asynchronous.  SL_E_STATE for Ising lattices. */
+sl_status sl_reset_persistence(sl_lattice* lat);
+
+/* Release the handle (never frees the borrowed buffer).  Synchronises. */
+sl_status sl_destroy(sl_lattice* lat);
+
+/* Observables of n records (host-only, pure, double precision): Ising
+ * E = -J bond_sum - h mag (Eq. 2 with a field), M = mag, P = NaN; NE (J = 0,
+ * one unit of energy per up site, Eq. 3 read with n in {0,1}): E = mag,
+ * M = mag, P = unflipped / L^dim (persistence).  Any output may be NULL. */
+sl_status sl_record_observables(const sl_params* params, const sl_record* records, size_t n,
+                                double* E, double* M, double* P);
+
+const char* sl_status_str(sl_status status);
+const char* sl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPINLAT_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) checkerboard Metropolis sweep for lattice spin models.
+
+Hot path of "Simulating lattice spin models on GPUs" (Levy, Cohen & Rabani,
+arXiv:1209.0296): sub-lattice-parallel Metropolis sweeps of the spin-1/2 and
+spin-1 Ising model in 2D/3D and of the North-East facilitated model, in
+hand-written HIP kernels behind the C ABI of ``include/spinlat.h``.
+"""
+from .spinlat import (  # noqa: F401
+    ABI_VERSION, EXPORTS, INIT_BUFFER, INIT_COLD, INIT_RANDOM, ISING, MODE_AUTO, MODE_FUSED,
+    MODE_HALF, MODE_SIMPLE, NORTH_EAST, RECORD_DTYPE, Lattice, Params, SpinlatError, lib,
+    query_bytes, records_to_array, threshold_table,
+)

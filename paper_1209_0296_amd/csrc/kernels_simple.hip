@@ -1,0 +1,300 @@
+// kernels_simple.hip -- initial state, layout conversion, record folding and
+// the direct (no LDS) half-sweep kernel for gfx950.
+//
+// Layout: two colour arrays of L^dim/2 int8 sites (see spinlat_internal.h).
+// One thread owns one 4-byte word = 4 consecutive same-colour sites of one row
+// (Lh % 4 == 0), which is exactly the set of sites one Philox4x32-10 call
+// serves for one-word moves (spin-1/2, NE) and two calls serve for spin-1.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+#include "site_update.hpp"
+#include "spinlat_internal.h"
+
+namespace spinlat {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+
+// ---------------------------------------------------------------------------
+// Initial state (Alg. I step 1; NE: up with probability c, Sec. 3.2), drawn
+// from Philox with tag 1 at sweep 0.  mode: 0 cold (+1), 1 random.
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_init(SweepArgs a, int mode, uint32_t thr_lo,
+                                                 uint32_t thr_hi)
+{
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gi >= 2 * ngroups) return;
+    const uint32_t c = gi >= ngroups ? 1u : 0u;
+    const uint64_t g = gi - (c ? ngroups : 0);
+    const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+    const Words4 r = philox4x32_10((uint32_t)g, c, 0u, 1u, ks);
+    const uint64_t thr = ((uint64_t)thr_hi << 32) | thr_lo;
+    uint32_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t u = r.w[b];
+        int v;
+        if (KIND == KIND_NE) {
+            v = ((uint64_t)u < thr) ? 1 : 0;
+        } else if (mode == 0) {
+            v = 1;
+        } else if (KIND == KIND_ISING_HALF) {
+            v = (u < 0x80000000u) ? 1 : -1;
+        } else {
+            v = (int)(((uint64_t)u * 3u) >> 32) - 1;
+        }
+        word |= ((uint32_t)(uint8_t)(int8_t)v) << (8 * b);
+    }
+    *reinterpret_cast<uint32_t*>(a.col[c] + 4 * g) = word;
+}
+
+// Natural row-major bytes <-> colour arrays.
+__device__ __forceinline__ uint64_t natural_index(const Geom& g, uint32_t c, uint64_t k)
+{
+    const uint64_t row = k / g.Lh;
+    const uint32_t kk = (uint32_t)(k - row * g.Lh);
+    const uint32_t y = (uint32_t)(row % g.L);
+    const uint32_t z = (uint32_t)(row / g.L);
+    const uint32_t x = 2 * kk + ((y + z + c) & 1u);
+    return row * g.L + x;
+}
+
+__global__ void __launch_bounds__(kBlock) k_from_natural(SweepArgs a, const int8_t* nat)
+{
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gi >= 2 * ngroups) return;
+    const uint32_t c = gi >= ngroups ? 1u : 0u;
+    const uint64_t g = gi - (c ? ngroups : 0);
+    uint32_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        word |= (uint32_t)(uint8_t)nat[natural_index(a.g, c, 4 * g + b)] << (8 * b);
+    *reinterpret_cast<uint32_t*>(a.col[c] + 4 * g) = word;
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_natural(SweepArgs a, int8_t* nat)
+{
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gi >= 2 * ngroups) return;
+    const uint32_t c = gi >= ngroups ? 1u : 0u;
+    const uint64_t g = gi - (c ? ngroups : 0);
+    const uint32_t word = *reinterpret_cast<const uint32_t*>(a.col[c] + 4 * g);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        nat[natural_index(a.g, c, 4 * g + b)] = (int8_t)(uint8_t)(word >> (8 * b));
+}
+
+__global__ void __launch_bounds__(kBlock) k_clear_flags(SweepArgs a)
+{
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gi >= 2 * ngroups) return;
+    const uint32_t c = gi >= ngroups ? 1u : 0u;
+    const uint64_t g = gi - (c ? ngroups : 0);
+    uint32_t* p = reinterpret_cast<uint32_t*>(a.col[c] + 4 * g);
+    *p = *p & 0x01010101u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Sum the kSub sub-slots of each pending record, write {t, q0..q3} and clear
+// the accumulators for reuse.
+__global__ void __launch_bounds__(kBlock) k_fold(unsigned long long* acc, int64_t* out, uint64_t n,
+                                                 uint64_t t_first, int ising)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long* slot = acc + i * kSlotWords;
+    int64_t sum[kQ] = {0, 0, 0, 0};
+    for (int s = 0; s < kSub; ++s)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            sum[q] += (int64_t)slot[s * kQ + q];
+            slot[s * kQ + q] = 0ull;
+        }
+    int64_t* o = out + i * kRecordWords;
+    o[0] = (int64_t)(t_first + i);
+    o[1] = sum[0];
+    o[2] = sum[1];
+    o[3] = sum[2];
+    o[4] = ising ? -1 : sum[3];
+}
+
+// ---------------------------------------------------------------------------
+// Direct half-sweep: each thread updates its 4 sites reading the neighbours
+// straight from the other colour array.  With update == 0 it only
+// accumulates the observables of the current state (record r_0).
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
+{
+    __shared__ uint64_t lut[kMaxLut];
+    for (int i = threadIdx.x; i < a.lut_n; i += kBlock) lut[i] = a.lut[i];
+    __syncthreads();
+
+    const Geom g = a.g;
+    const uint64_t ngroups = g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t q_bond = 0, q_mag = 0, q_acc = 0, q_unfl = 0;
+    if (gi < ngroups) {
+        const uint32_t c = a.colour;
+        uint8_t* own = a.col[c];
+        const int8_t* oth = reinterpret_cast<const int8_t*>(a.col[c ^ 1u]);
+        const uint64_t k0 = gi * 4;
+        const uint64_t row = k0 / g.Lh;
+        const uint32_t kk0 = (uint32_t)(k0 - row * g.Lh);
+        const uint32_t y = (uint32_t)(row % g.L);
+        const uint32_t zc = DIM == 3 ? (uint32_t)(row / g.L) : 0u;
+        const uint32_t p = (y + zc + c) & 1u;
+        const uint64_t r_ym = (uint64_t)zc * g.L + wrap_dec(y, g.L);
+        const uint64_t r_yp = (uint64_t)zc * g.L + wrap_inc(y, g.L);
+        const uint64_t r_zm = (uint64_t)wrap_dec(zc, g.L) * g.L + y;
+        const uint64_t r_zp = (uint64_t)wrap_inc(zc, g.L) * g.L + y;
+
+        const uint32_t cur = *reinterpret_cast<const uint32_t*>(own + k0);
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        Words4 wa = {{0, 0, 0, 0}}, wb = {{0, 0, 0, 0}};
+        if (a.update) {
+            if (KIND == KIND_ISING_ONE) {
+                wa = philox4x32_10((uint32_t)(2 * gi), c, a.t, 0u, ks);
+                wb = philox4x32_10((uint32_t)(2 * gi + 1), c, a.t, 0u, ks);
+            } else {
+                wa = philox4x32_10((uint32_t)gi, c, a.t, 0u, ks);
+            }
+        }
+        constexpr int z = 2 * DIM;
+        uint32_t out = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t kk = kk0 + b;
+            const uint32_t kside = p ? wrap_inc(kk, g.Lh) : wrap_dec(kk, g.Lh);
+            const int sv = (int)(int8_t)(uint8_t)(cur >> (8 * b));
+            int nv;
+            if (KIND == KIND_NE) {
+                const int north = oth[r_ym * g.Lh + kk];
+                const int east = oth[row * g.Lh + (p ? kside : kk)];
+                nv = a.update ? move_ne(sv, north, east, wa.w[b], lut[0], lut[1]) : sv;
+                q_mag += nv & 1;
+                q_unfl += (nv & 2) ? 0 : 1;
+                if (c == 1) {
+                    const int south = oth[r_yp * g.Lh + kk];
+                    const int west = oth[row * g.Lh + (p ? kk : kside)];
+                    q_bond += (nv & 1) * ((north & 1) + (east & 1) + (south & 1) + (west & 1));
+                }
+            } else {
+                int nsum = oth[row * g.Lh + kk] + oth[row * g.Lh + kside] + oth[r_ym * g.Lh + kk] +
+                           oth[r_yp * g.Lh + kk];
+                if (DIM == 3) nsum += oth[r_zm * g.Lh + kk] + oth[r_zp * g.Lh + kk];
+                if (!a.update) {
+                    nv = sv;
+                } else if (KIND == KIND_ISING_HALF) {
+                    nv = move_ising_half(sv, nsum, wa.w[b], lut, z);
+                } else {
+                    const Words4& w = (b < 2) ? wa : wb;
+                    nv = move_ising_one(sv, nsum, w.w[(b & 1) * 2], w.w[(b & 1) * 2 + 1], lut, z);
+                }
+                q_mag += nv;
+                if (c == 1) q_bond += nv * nsum;
+            }
+            q_acc += (nv != sv) ? 1 : 0;
+            out |= (uint32_t)(uint8_t)(int8_t)nv << (8 * b);
+        }
+        if (a.update) *reinterpret_cast<uint32_t*>(own + k0) = out;
+    }
+    block_accumulate(q_bond, q_mag, q_acc, q_unfl, a.acc);
+}
+
+inline unsigned blocks_for(uint64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const SweepArgs& a, int kind, int init_mode, uint32_t thr_lo,
+                       uint32_t thr_hi, hipStream_t s)
+{
+    const unsigned nb = blocks_for(2 * (a.g.nh >> 2));
+    switch (kind) {
+        case KIND_ISING_HALF:
+            hipLaunchKernelGGL(k_init<KIND_ISING_HALF>, dim3(nb), dim3(kBlock), 0, s, a, init_mode,
+                               thr_lo, thr_hi);
+            break;
+        case KIND_ISING_ONE:
+            hipLaunchKernelGGL(k_init<KIND_ISING_ONE>, dim3(nb), dim3(kBlock), 0, s, a, init_mode,
+                               thr_lo, thr_hi);
+            break;
+        default:
+            hipLaunchKernelGGL(k_init<KIND_NE>, dim3(nb), dim3(kBlock), 0, s, a, init_mode, thr_lo,
+                               thr_hi);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_from_natural(const SweepArgs& a, const int8_t* nat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_from_natural, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a,
+                       nat);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_natural, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a,
+                       nat);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags(const SweepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_flags, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(unsigned long long* acc, int64_t* out, uint64_t n, uint64_t t_first,
+                       int ising, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(kBlock), 0, s, acc, out, n, t_first,
+                       ising);
+    return hipGetLastError();
+}
+
+hipError_t launch_simple_half(const SweepArgs& a, int kind, hipStream_t s)
+{
+    const dim3 grid(blocks_for(a.g.nh >> 2));
+    const dim3 block(kBlock);
+    if (kind == KIND_NE) {
+        hipLaunchKernelGGL((k_simple_half<KIND_NE, 2>), grid, block, 0, s, a);
+    } else if (a.g.dim == 2) {
+        if (kind == KIND_ISING_HALF)
+            hipLaunchKernelGGL((k_simple_half<KIND_ISING_HALF, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_simple_half<KIND_ISING_ONE, 2>), grid, block, 0, s, a);
+    } else {
+        if (kind == KIND_ISING_HALF)
+            hipLaunchKernelGGL((k_simple_half<KIND_ISING_HALF, 3>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_simple_half<KIND_ISING_ONE, 3>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spinlat

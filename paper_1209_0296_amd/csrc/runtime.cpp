@@ -1,0 +1,478 @@
+// runtime.cpp -- host side of the C ABI declared in include/spinlat.h.
+//
+// Responsibilities: validate parameters, lay out the caller's device buffer,
+// build the Metropolis threshold table in double precision (paper Sec. 3.1:
+// P_acc = min[1, exp(-dE/T)]; Sec. 3.2 for the NE model), enqueue the
+// kernels on the caller's stream (one sweep = colour 0 then colour 1, Alg. I
+// steps 5-7; a kernel boundary is the global barrier between the colours) and
+// drain the per-sweep record ring.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/spinlat.h"
+#include "spinlat_internal.h"
+
+using namespace spinlat;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sl_status fail(sl_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sl_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(SL_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    uint64_t nsites;   // L^dim
+    uint64_t nh;       // per colour
+    size_t col_bytes;  // one colour array, rounded to kAlign
+    size_t off_col1;
+    size_t off_acc;    // accumulators [capacity][kSub][kQ] int64
+    size_t off_out;    // folded records [capacity][5] int64
+    size_t off_lut;    // threshold table, kMaxLut u64
+    size_t total;
+};
+
+int kind_of(const sl_params* p)
+{
+    if (p->model == SL_NORTH_EAST) return KIND_NE;
+    return p->two_s == 1 ? KIND_ISING_HALF : KIND_ISING_ONE;
+}
+
+sl_status validate(const sl_params* p)
+{
+    if (!p) return fail(SL_E_INVALID, "params is NULL");
+    if (p->abi_version != SL_ABI_VERSION)
+        return fail(SL_E_INVALID, "abi_version %u != %u", p->abi_version, SL_ABI_VERSION);
+    if (p->model != SL_ISING && p->model != SL_NORTH_EAST)
+        return fail(SL_E_INVALID, "unknown model %d", p->model);
+    if (p->dim != 2 && p->dim != 3) return fail(SL_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->L < 2 || (p->L & 1))
+        return fail(SL_E_INVALID, "L must be even and >= 2 (got %d): the checkerboard needs a "
+                                  "bipartite periodic lattice", p->L);
+    if (p->two_s != 1 && p->two_s != 2)
+        return fail(SL_E_INVALID, "two_s must be 1 (spin-1/2) or 2 (spin-1), got %d", p->two_s);
+    if (p->init != SL_INIT_COLD && p->init != SL_INIT_RANDOM && p->init != SL_INIT_BUFFER)
+        return fail(SL_E_INVALID, "unknown init %d", p->init);
+    if (p->init == SL_INIT_BUFFER && !p->init_spins)
+        return fail(SL_E_INVALID, "SL_INIT_BUFFER needs init_spins");
+    if (p->model == SL_ISING) {
+        if (!(p->T > 0.0)) return fail(SL_E_INVALID, "T must be > 0 (got %g)", p->T);
+        if (std::isnan(p->J) || std::isnan(p->h) || std::isinf(p->J) || std::isinf(p->h))
+            return fail(SL_E_INVALID, "J and h must be finite");
+    } else {
+        if (p->dim != 2) return fail(SL_E_INVALID, "the North-East model is two-dimensional");
+        if (p->two_s != 1) return fail(SL_E_INVALID, "the North-East model has binary sites");
+        if (!(p->c > 0.0 && p->c < 1.0))
+            return fail(SL_E_INVALID, "c must lie in (0, 1) (got %g)", p->c);
+        if (p->init == SL_INIT_COLD)
+            return fail(SL_E_INVALID, "NE lattices start from Bernoulli(c) or a buffer");
+    }
+    if (p->t0 >= (1ull << 32)) return fail(SL_E_OVERFLOW, "t0 must be < 2^32");
+    if (p->record_capacity < 1 || p->record_capacity > (1ull << 32))
+        return fail(SL_E_INVALID, "record_capacity must be in [1, 2^32]");
+    if (p->L % 8 != 0)
+        return fail(SL_E_UNSUPPORTED, "kernels need L %% 8 == 0 (got %d)", p->L);
+    // the first counter word holds the Philox group index (k / G) in 32 bits
+    const uint64_t nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
+    const uint64_t groups = (nsites / 2) / (p->two_s == 1 ? 4 : 2);
+    if (groups > (1ull << 32))
+        return fail(SL_E_UNSUPPORTED, "lattice too large for the 32-bit Philox group index");
+    return SL_OK;
+}
+
+Layout layout_of(const sl_params* p)
+{
+    Layout l{};
+    l.nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
+    l.nh = l.nsites / 2;
+    l.col_bytes = round_up(l.nh, kAlign);
+    l.off_col1 = l.col_bytes;
+    l.off_acc = 2 * l.col_bytes;
+    l.off_out = l.off_acc + round_up(p->record_capacity * kSlotWords * sizeof(int64_t), kAlign);
+    l.off_lut = l.off_out + round_up(p->record_capacity * kRecordWords * sizeof(int64_t), kAlign);
+    l.total = l.off_lut + round_up(kMaxLut * sizeof(uint64_t), kAlign);
+    return l;
+}
+
+// ---- Metropolis thresholds (double precision, host) ------------------------
+
+uint64_t thr_from_prob(double pr)
+{
+    if (!(pr < 1.0)) return 1ull << 32;
+    if (!(pr > 0.0)) return 0;
+    return (uint64_t)std::floor(pr * 4294967296.0);
+}
+
+uint64_t thr_from_energy(double dE, double T)
+{
+    if (dE <= 0.0) return 1ull << 32;
+    return thr_from_prob(std::exp(-dE / T));
+}
+
+size_t build_table(const sl_params* p, uint64_t* out)
+{
+    if (p->model == SL_NORTH_EAST) {
+        out[0] = thr_from_prob(p->c / (1.0 - p->c));  // up-flip: energy +1
+        out[1] = thr_from_prob((1.0 - p->c) / p->c);  // down-flip
+        return 2;
+    }
+    const int z = 2 * p->dim;
+    const int ds_of[4] = {-2, -1, 1, 2};
+    size_t n = 0;
+    for (int di = 0; di < 4; ++di)
+        for (int nsum = -z; nsum <= z; ++nsum) {
+            const double dE = -(double)ds_of[di] * (p->J * (double)nsum + p->h);
+            out[n++] = thr_from_energy(dE, p->T);
+        }
+    return n;
+}
+
+}  // namespace
+
+struct sl_lattice {
+    sl_params params;
+    Layout lay;
+    uint8_t* base;
+    hipStream_t stream;
+    int kind;
+    uint64_t next_t;   // index of the next sweep
+    uint64_t pending;  // unread records
+    uint64_t first_t;  // t of the oldest unread record
+    sl_launch launch;
+    uint64_t table[kMaxLut];
+    size_t table_n;
+};
+
+namespace {
+
+SweepArgs args_of(const sl_lattice* h)
+{
+    SweepArgs a{};
+    a.col[0] = h->base;
+    a.col[1] = h->base + h->lay.off_col1;
+    a.g.L = (uint32_t)h->params.L;
+    a.g.Lh = (uint32_t)(h->params.L / 2);
+    a.g.dim = (uint32_t)h->params.dim;
+    a.g.rows = h->params.dim == 2 ? a.g.L : a.g.L * a.g.L;
+    a.g.nh = h->lay.nh;
+    a.key0 = (uint32_t)h->params.seed;
+    a.key1 = (uint32_t)(h->params.seed >> 32);
+    a.lut = reinterpret_cast<const uint64_t*>(h->base + h->lay.off_lut);
+    a.lut_n = (int32_t)h->table_n;
+    a.update = 1;
+    a.tile_rows = h->launch.tile_rows;
+    a.tile_words = h->launch.tile_words;
+    return a;
+}
+
+unsigned long long* slot_ptr(const sl_lattice* h, uint64_t idx)
+{
+    return reinterpret_cast<unsigned long long*>(h->base + h->lay.off_acc) + idx * kSlotWords;
+}
+
+// Default schedule for a shape.
+sl_launch auto_launch(const sl_lattice* h)
+{
+    sl_launch l{};
+    l.mode = SL_MODE_SIMPLE;
+    l.tile_rows = 0;
+    l.tile_words = 0;
+    (void)h;
+    return l;
+}
+
+sl_status check_launch(const sl_lattice* h, const sl_launch* l)
+{
+    if (l->mode == SL_MODE_SIMPLE) return SL_OK;
+    if (l->mode == SL_MODE_HALF || l->mode == SL_MODE_FUSED) {
+        SweepArgs a = args_of(h);
+        if (!tiled_supported(a.g, h->kind, l->tile_rows, l->tile_words, l->mode == SL_MODE_FUSED))
+            return fail(SL_E_UNSUPPORTED, "tile %d rows x %d words not supported for this shape "
+                                          "and mode %d", l->tile_rows, l->tile_words, l->mode);
+        return SL_OK;
+    }
+    return fail(SL_E_INVALID, "unknown launch mode %d", l->mode);
+}
+
+// Record of the current state without any update (r_0): both colours with
+// update = 0 through the direct kernel.
+sl_status enqueue_observe(sl_lattice* h, uint64_t slot)
+{
+    SweepArgs a = args_of(h);
+    a.update = 0;
+    a.acc = slot_ptr(h, slot);
+    for (uint32_t c = 0; c < 2; ++c) {
+        a.colour = c;
+        hipError_t e = launch_simple_half(a, h->kind, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "observe kernel");
+    }
+    return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sl_status sl_query_bytes(const sl_params* params, size_t* device_bytes)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK) return st;
+    if (!device_bytes) return fail(SL_E_INVALID, "device_bytes is NULL");
+    *device_bytes = layout_of(params).total;
+    return SL_OK;
+}
+
+sl_status sl_threshold_table(const sl_params* params, uint64_t* out, size_t cap, size_t* n_out)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK) return st;
+    uint64_t tmp[kMaxLut];
+    const size_t n = build_table(params, tmp);
+    if (n_out) *n_out = n;
+    if (!out || cap < n) return fail(SL_E_BUFFER, "table needs %zu entries", n);
+    std::memcpy(out, tmp, n * sizeof(uint64_t));
+    return SL_OK;
+}
+
+sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t bytes,
+                            void* hip_stream, sl_lattice** out)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK) return st;
+    if (!out) return fail(SL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const Layout lay = layout_of(params);
+    if (!device_buf) return fail(SL_E_BUFFER, "device buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(device_buf) % kAlign != 0)
+        return fail(SL_E_BUFFER, "device buffer must be %zu-byte aligned", kAlign);
+    if (bytes < lay.total)
+        return fail(SL_E_BUFFER, "device buffer has %zu bytes, needs %zu", bytes, lay.total);
+
+    sl_lattice* h = new (std::nothrow) sl_lattice();
+    if (!h) return fail(SL_E_STATE, "out of host memory");
+    h->params = *params;
+    h->lay = lay;
+    h->base = static_cast<uint8_t*>(device_buf);
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->kind = kind_of(params);
+    h->next_t = params->t0;
+    h->pending = 0;
+    h->first_t = params->t0;
+    h->table_n = build_table(params, h->table);
+    h->launch = auto_launch(h);
+
+    hipError_t e = hipMemcpyAsync(h->base + lay.off_lut, h->table, h->table_n * sizeof(uint64_t),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = launch_fill_u64(slot_ptr(h, 0), params->record_capacity * kSlotWords, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "create: table upload / ring clear");
+    }
+    SweepArgs a = args_of(h);
+    if (params->init == SL_INIT_BUFFER) {
+        e = launch_from_natural(a, params->init_spins, h->stream);
+    } else {
+        const uint64_t bern = thr_from_prob(params->c);
+        e = launch_init(a, h->kind, params->init == SL_INIT_COLD ? 0 : 1, (uint32_t)bern,
+                        (uint32_t)(bern >> 32), h->stream);
+    }
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "create: initial state");
+    }
+    st = enqueue_observe(h, 0);
+    if (st != SL_OK) {
+        delete h;
+        return st;
+    }
+    h->pending = 1;
+    // the table upload reads h->table; keep it alive until the copy is done
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "create: synchronise");
+    }
+    *out = h;
+    return SL_OK;
+}
+
+sl_status sl_set_launch(sl_lattice* h, const sl_launch* launch)
+{
+    if (!h || !launch) return fail(SL_E_INVALID, "NULL argument");
+    sl_launch l = *launch;
+    if (l.mode == SL_MODE_AUTO) l = auto_launch(h);
+    sl_status st = check_launch(h, &l);
+    if (st != SL_OK) return st;
+    h->launch = l;
+    return SL_OK;
+}
+
+sl_status sl_get_launch(const sl_lattice* h, sl_launch* launch)
+{
+    if (!h || !launch) return fail(SL_E_INVALID, "NULL argument");
+    *launch = h->launch;
+    return SL_OK;
+}
+
+sl_status sl_sweep(sl_lattice* h, uint64_t n)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    if (n == 0) return SL_OK;
+    if (h->pending + n > h->params.record_capacity)
+        return fail(SL_E_STATE, "%llu unread records + %llu sweeps exceed record_capacity %llu; "
+                                "call sl_measure first", (unsigned long long)h->pending,
+                    (unsigned long long)n, (unsigned long long)h->params.record_capacity);
+    if (h->next_t + n > (1ull << 32))
+        return fail(SL_E_OVERFLOW, "sweep index would reach 2^32");
+    SweepArgs a = args_of(h);
+    for (uint64_t i = 0; i < n; ++i) {
+        a.t = (uint32_t)(h->next_t + i);
+        a.acc = slot_ptr(h, h->pending + i);
+        hipError_t e = hipSuccess;
+        switch (h->launch.mode) {
+            case SL_MODE_FUSED:
+                e = launch_fused_sweep(a, h->kind, h->stream);
+                break;
+            case SL_MODE_HALF:
+                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
+                    a.colour = c;
+                    e = launch_tiled_half(a, h->kind, h->stream);
+                }
+                break;
+            default:
+                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
+                    a.colour = c;
+                    e = launch_simple_half(a, h->kind, h->stream);
+                }
+                break;
+        }
+        if (e != hipSuccess) {
+            // sweeps before i were enqueued and will produce their records
+            h->next_t += i;
+            h->pending += i;
+            return hip_fail(e, "sweep launch");
+        }
+    }
+    h->next_t += n;
+    h->pending += n;
+    return SL_OK;
+}
+
+sl_status sl_measure(sl_lattice* h, sl_record* out, size_t cap, size_t* n_out)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    if (n_out) *n_out = 0;
+    const uint64_t n = h->pending;
+    if (n == 0) return SL_OK;
+    if (!out || cap < n)
+        return fail(SL_E_BUFFER, "%llu records pending, buffer holds %zu", (unsigned long long)n,
+                    cap);
+    int64_t* dev_out = reinterpret_cast<int64_t*>(h->base + h->lay.off_out);
+    hipError_t e = launch_fold(slot_ptr(h, 0), dev_out, n, h->first_t,
+                               h->params.model == SL_ISING ? 1 : 0, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dev_out, n * sizeof(sl_record), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "measure");
+    static_assert(sizeof(sl_record) == kRecordWords * sizeof(int64_t), "record layout");
+    h->first_t += n;
+    h->pending = 0;
+    if (n_out) *n_out = n;
+    return SL_OK;
+}
+
+sl_status sl_status_counts(const sl_lattice* h, uint64_t* pending, uint64_t* next_t)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    if (pending) *pending = h->pending;
+    if (next_t) *next_t = h->next_t;
+    return SL_OK;
+}
+
+sl_status sl_copy_spins(sl_lattice* h, int8_t* device_out, size_t n)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    if (!device_out || n < h->lay.nsites)
+        return fail(SL_E_BUFFER, "copy_spins needs %llu bytes", (unsigned long long)h->lay.nsites);
+    hipError_t e = launch_to_natural(args_of(h), device_out, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy_spins");
+    return SL_OK;
+}
+
+sl_status sl_reset_persistence(sl_lattice* h)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    if (h->params.model != SL_NORTH_EAST)
+        return fail(SL_E_STATE, "persistence is tracked for the North-East model only");
+    hipError_t e = launch_clear_flags(args_of(h), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "reset_persistence");
+    return SL_OK;
+}
+
+sl_status sl_destroy(sl_lattice* h)
+{
+    if (!h) return fail(SL_E_INVALID, "NULL lattice");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    delete h;
+    if (e != hipSuccess) return hip_fail(e, "destroy: synchronise");
+    return SL_OK;
+}
+
+sl_status sl_record_observables(const sl_params* params, const sl_record* records, size_t n,
+                                double* E, double* M, double* P)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK && st != SL_E_UNSUPPORTED) return st;
+    if (n && !records) return fail(SL_E_INVALID, "records is NULL");
+    const double nsites = (double)layout_of(params).nsites;
+    for (size_t i = 0; i < n; ++i) {
+        const sl_record& r = records[i];
+        if (params->model == SL_ISING) {
+            if (E) E[i] = -params->J * (double)r.bond_sum - params->h * (double)r.mag;
+            if (P) P[i] = std::nan("");
+        } else {
+            if (E) E[i] = (double)r.mag;
+            if (P) P[i] = (double)r.unflipped / nsites;
+        }
+        if (M) M[i] = (double)r.mag;
+    }
+    return SL_OK;
+}
+
+const char* sl_status_str(sl_status s)
+{
+    switch (s) {
+        case SL_OK: return "SL_OK";
+        case SL_E_INVALID: return "SL_E_INVALID";
+        case SL_E_UNSUPPORTED: return "SL_E_UNSUPPORTED";
+        case SL_E_BUFFER: return "SL_E_BUFFER";
+        case SL_E_HIP: return "SL_E_HIP";
+        case SL_E_STATE: return "SL_E_STATE";
+        case SL_E_OVERFLOW: return "SL_E_OVERFLOW";
+    }
+    return "SL_E_UNKNOWN";
+}
+
+const char* sl_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// spinlat_internal.h -- shared between the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spinlat {
+
+// Per-record accumulators: kSub sub-slots spread the workgroups' atomics over
+// several addresses (and cache lines); each holds kQ int64 quantities.
+constexpr int kSub = 16;
+constexpr int kQ = 4;  // bond_sum, mag, accepted, unflipped
+constexpr int kSlotWords = kSub * kQ;
+constexpr int kRecordWords = 5;  // t, bond_sum, mag, accepted, unflipped
+constexpr int kMaxLut = 64;      // >= 4*(4*3+1) = 52 Ising entries
+
+enum Kind : int { KIND_ISING_HALF = 0, KIND_ISING_ONE = 1, KIND_NE = 2 };
+
+// Geometry of the colour-split layout.  Natural site (x, y, z) has colour
+// (x+y+z)&1 and in-colour index k = ((z*L + y)*L + x) >> 1; the colour array
+// holds row r = z*L + y at bytes [r*Lh, (r+1)*Lh), Lh = L/2, and row r of
+// colour c holds x = 2*kk + ((y+z+c)&1).
+struct Geom {
+    uint32_t L;
+    uint32_t Lh;
+    uint32_t dim;
+    uint32_t rows;  // L (2D) or L*L (3D)
+    uint64_t nh;    // sites per colour = rows * Lh
+};
+
+struct SweepArgs {
+    uint8_t* col[2];          // colour arrays (device)
+    Geom g;
+    uint32_t key0, key1;      // Philox key = seed
+    uint32_t t;               // sweep index
+    uint32_t colour;          // half-sweep colour (SIMPLE/HALF modes)
+    int32_t update;           // 0: only accumulate observables (record r_0)
+    int32_t lut_n;
+    unsigned long long* acc;  // record slot [kSub][kQ]
+    const uint64_t* lut;      // threshold table (device), lut_n entries
+    // LDS-tiled modes
+    int32_t tile_rows;
+    int32_t tile_words;
+};
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
+hipError_t launch_init(const SweepArgs& a, int kind, int init_mode, uint32_t bern_thr_lo,
+                       uint32_t bern_thr_hi, hipStream_t s);
+hipError_t launch_from_natural(const SweepArgs& a, const int8_t* nat, hipStream_t s);
+hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s);
+hipError_t launch_clear_flags(const SweepArgs& a, hipStream_t s);
+hipError_t launch_simple_half(const SweepArgs& a, int kind, hipStream_t s);
+hipError_t launch_tiled_half(const SweepArgs& a, int kind, hipStream_t s);
+hipError_t launch_fused_sweep(const SweepArgs& a, int kind, hipStream_t s);
+hipError_t launch_fold(unsigned long long* acc, int64_t* out, uint64_t n, uint64_t t_first,
+                       int ising, hipStream_t s);
+
+// Shape limits of the tiled kernels (checked by the runtime before launch).
+bool tiled_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused);
+
+}  // namespace spinlat

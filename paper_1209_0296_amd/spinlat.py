@@ -1,0 +1,265 @@
+"""ctypes binding of the C ABI in ``include/spinlat.h``.
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+``libspinlat.so``.  PyTorch provides the device buffer and the stream.  If
+the library has not been built the import of this module fails loudly; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspinlat.so")
+
+ABI_VERSION = 1
+ISING, NORTH_EAST = 0, 1
+INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
+MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
+STATUS = {0: "SL_OK", 1: "SL_E_INVALID", 2: "SL_E_UNSUPPORTED", 3: "SL_E_BUFFER",
+          4: "SL_E_HIP", 5: "SL_E_STATE", 6: "SL_E_OVERFLOW"}
+
+# every symbol include/spinlat.h declares
+EXPORTS = (
+    "sl_query_bytes", "sl_threshold_table", "sl_create_lattice", "sl_set_launch",
+    "sl_get_launch", "sl_sweep", "sl_measure", "sl_status_counts", "sl_copy_spins",
+    "sl_reset_persistence", "sl_destroy", "sl_status_str", "sl_last_error",
+    "sl_record_observables",
+)
+
+
+class SpinlatError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("model", ctypes.c_int32), ("dim", ctypes.c_int32),
+        ("L", ctypes.c_int32), ("two_s", ctypes.c_int32), ("init", ctypes.c_int32),
+        ("J", ctypes.c_double), ("h", ctypes.c_double), ("T", ctypes.c_double),
+        ("c", ctypes.c_double), ("seed", ctypes.c_uint64), ("t0", ctypes.c_uint64),
+        ("record_capacity", ctypes.c_uint64), ("init_spins", ctypes.c_void_p),
+    ]
+
+
+class CRecord(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint64), ("bond_sum", ctypes.c_int64), ("mag", ctypes.c_int64),
+                ("accepted", ctypes.c_int64), ("unflipped", ctypes.c_int64)]
+
+
+class CLaunch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_words", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspinlat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1209_0296_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, H = ctypes.POINTER(CParams), ctypes.c_void_p
+    sz = ctypes.c_size_t
+    L.sl_query_bytes.argtypes = [P, ctypes.POINTER(sz)]
+    L.sl_threshold_table.argtypes = [P, ctypes.c_void_p, sz, ctypes.POINTER(sz)]
+    L.sl_create_lattice.argtypes = [P, ctypes.c_void_p, sz, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    L.sl_set_launch.argtypes = [H, ctypes.POINTER(CLaunch)]
+    L.sl_get_launch.argtypes = [H, ctypes.POINTER(CLaunch)]
+    L.sl_sweep.argtypes = [H, ctypes.c_uint64]
+    L.sl_measure.argtypes = [H, ctypes.c_void_p, sz, ctypes.POINTER(sz)]
+    L.sl_status_counts.argtypes = [H, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    L.sl_copy_spins.argtypes = [H, ctypes.c_void_p, sz]
+    L.sl_reset_persistence.argtypes = [H]
+    L.sl_destroy.argtypes = [H]
+    L.sl_status_str.argtypes = [ctypes.c_int]
+    L.sl_status_str.restype = ctypes.c_char_p
+    L.sl_last_error.argtypes = []
+    L.sl_last_error.restype = ctypes.c_char_p
+    L.sl_record_observables.argtypes = [P, ctypes.c_void_p, sz, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("sl_status_str", "sl_last_error"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise SpinlatError(status, lib().sl_last_error().decode())
+
+
+@dataclass
+class Params:
+    """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1; 2D or
+    3D) or the North-East model (up-density c; 2D)."""
+    model: int = ISING
+    dim: int = 2
+    L: int = 64
+    two_s: int = 1
+    J: float = 1.0
+    h: float = 0.0
+    T: float = 2.269
+    c: float = 0.1
+    seed: int = 1
+    init: int = INIT_RANDOM
+    t0: int = 0
+    record_capacity: int = 1024
+
+    def c_struct(self, init_spins_ptr: int = 0) -> CParams:
+        return CParams(ABI_VERSION, self.model, self.dim, self.L, self.two_s, self.init,
+                       float(self.J), float(self.h), float(self.T), float(self.c),
+                       int(self.seed), int(self.t0), int(self.record_capacity),
+                       init_spins_ptr or None)
+
+    @property
+    def nsites(self) -> int:
+        return self.L ** self.dim
+
+    @property
+    def shape(self):
+        return (self.L,) * self.dim
+
+
+def query_bytes(p: Params) -> int:
+    n = ctypes.c_size_t()
+    cp = p.c_struct(1 if p.init == INIT_BUFFER else 0)
+    _check(lib().sl_query_bytes(ctypes.byref(cp), ctypes.byref(n)))
+    return n.value
+
+
+def threshold_table(p: Params) -> np.ndarray:
+    out = np.zeros(64, dtype=np.uint64)
+    n = ctypes.c_size_t()
+    cp = p.c_struct(1 if p.init == INIT_BUFFER else 0)
+    _check(lib().sl_threshold_table(ctypes.byref(cp), out.ctypes.data, out.size, ctypes.byref(n)))
+    return out[: n.value].copy()
+
+
+RECORD_DTYPE = np.dtype([("t", np.uint64), ("bond_sum", np.int64), ("mag", np.int64),
+                         ("accepted", np.int64), ("unflipped", np.int64)])
+
+
+class Lattice:
+    """One lattice resident in HBM, advanced by ``sweep`` and read by ``measure``.
+
+    The device buffer is a torch uint8 tensor owned by this object; work goes
+    on ``stream`` (default: torch's current stream on ``device``).
+    """
+
+    def __init__(self, params: Params, init_spins=None, device="cuda", stream=None):
+        import torch
+
+        self.params = params
+        self.device = torch.device(device)
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ptr = 0
+        if params.init == INIT_BUFFER:
+            if init_spins is None:
+                raise ValueError("INIT_BUFFER needs init_spins")
+            init_spins = init_spins.to(device=self.device, dtype=torch.int8).contiguous()
+            if init_spins.numel() != params.nsites:
+                raise ValueError("init_spins has the wrong size")
+            self._init_spins = init_spins
+            ptr = init_spins.data_ptr()
+        nbytes = query_bytes(params)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cp = params.c_struct(ptr)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().sl_create_lattice(ctypes.byref(cp), self.buffer.data_ptr(), nbytes,
+                                           self.stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+
+    # -- schedule -----------------------------------------------------------
+    def set_launch(self, mode: int, tile_rows: int = 0, tile_words: int = 0) -> None:
+        _check(lib().sl_set_launch(self._h, ctypes.byref(CLaunch(mode, tile_rows, tile_words, 0))))
+
+    def get_launch(self):
+        l = CLaunch()
+        _check(lib().sl_get_launch(self._h, ctypes.byref(l)))
+        return (l.mode, l.tile_rows, l.tile_words)
+
+    # -- the hot path -------------------------------------------------------
+    def sweep(self, n: int) -> None:
+        _check(lib().sl_sweep(self._h, int(n)))
+
+    def counts(self):
+        p, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sl_status_counts(self._h, ctypes.byref(p), ctypes.byref(t)))
+        return p.value, t.value
+
+    def measure(self) -> np.ndarray:
+        """Drain the unread per-sweep records (synchronises the stream)."""
+        pending, _ = self.counts()
+        out = np.zeros(max(pending, 1), dtype=RECORD_DTYPE)
+        n = ctypes.c_size_t()
+        _check(lib().sl_measure(self._h, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out[: n.value]
+
+    def observables(self, records: np.ndarray):
+        """E, M and persistence per record, computed by the library (double)."""
+        n = len(records)
+        E = np.zeros(n)
+        M = np.zeros(n)
+        P = np.zeros(n)
+        recs = np.ascontiguousarray(records)
+        cp = self.params.c_struct(1 if self.params.init == INIT_BUFFER else 0)
+        _check(lib().sl_record_observables(ctypes.byref(cp), recs.ctypes.data, n,
+                                           E.ctypes.data, M.ctypes.data, P.ctypes.data))
+        return E, M, P
+
+    def copy_spins(self):
+        """Device int8 tensor of the lattice in natural order, shape (L,)*dim."""
+        torch = self._torch
+        out = torch.empty(self.params.nsites, dtype=torch.int8, device=self.device)
+        _check(lib().sl_copy_spins(self._h, out.data_ptr(), out.numel()))
+        return out.view(*self.params.shape)
+
+    def spins(self) -> np.ndarray:
+        """Host copy (numpy int8, natural order) -- synchronises."""
+        t = self.copy_spins()
+        self.stream.synchronize()
+        return t.cpu().numpy()
+
+    def reset_persistence(self) -> None:
+        _check(lib().sl_reset_persistence(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib().sl_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def records_to_array(records: np.ndarray) -> np.ndarray:
+    """Structured records -> (n, 5) int64 array {t, bond_sum, mag, accepted, unflipped}."""
+    return np.stack([records[f].astype(np.int64) for f in RECORD_DTYPE.names], axis=1)

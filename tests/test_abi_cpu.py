@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/spinlat.h declares, parameter validation,
+buffer sizing, and the threshold table against the oracle's."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1209_0296_amd as S
+from paper_1209_0296_amd import spinlat as B
+from helpers import oracle_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "spinlat.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl_\w+)\s*\(", txt)))
+
+
+def test_header_declarations_are_exported():
+    names = _declared()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def _status(p):
+    n = ctypes.c_size_t()
+    cp = p.c_struct(1 if p.init == S.INIT_BUFFER else 0)
+    return S.lib().sl_query_bytes(ctypes.byref(cp), ctypes.byref(n)), n.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(L=63), 1), (dict(L=0), 1), (dict(L=12), 2), (dict(dim=4), 1), (dict(two_s=3), 1),
+    (dict(T=0.0), 1), (dict(T=-1.0), 1), (dict(T=float("nan")), 1),
+    (dict(model=1, c=0.0), 1), (dict(model=1, c=1.0), 1), (dict(model=1, dim=3), 1),
+    (dict(model=1, two_s=2), 1), (dict(model=1, init=S.INIT_COLD), 1), (dict(init=7), 1),
+    (dict(t0=2 ** 32), 6), (dict(record_capacity=0), 1), (dict(model=7), 1),
+])
+def test_invalid_parameters_rejected(kw, code):
+    st, _ = _status(S.Params(**kw))
+    assert st == code, S.lib().sl_last_error()
+    assert S.lib().sl_last_error()
+
+
+def test_abi_version_checked():
+    cp = S.Params().c_struct()
+    cp.abi_version = 99
+    n = ctypes.c_size_t()
+    assert S.lib().sl_query_bytes(ctypes.byref(cp), ctypes.byref(n)) == 1
+
+
+def test_buffer_size_covers_lattice_and_ring():
+    for p in (S.Params(L=64), S.Params(dim=3, L=256), S.Params(L=8192, record_capacity=10000)):
+        st, n = _status(p)
+        assert st == 0
+        assert n >= p.nsites + p.record_capacity * (16 * 4 * 8 + 40)
+
+
+def test_infinite_temperature_allowed():
+    assert _status(S.Params(T=math.inf))[0] == 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(T=2.0), dict(T=2.269), dict(T=2.6), dict(T=0.3), dict(T=math.inf), dict(T=1.5, h=0.37),
+    dict(T=1.1, J=-1.0, h=0.2), dict(dim=3, T=4.5115), dict(two_s=2, T=1.6935),
+    dict(dim=3, two_s=2, T=3.19, h=-0.5), dict(model=1, c=0.05), dict(model=1, c=0.1),
+    dict(model=1, c=0.2), dict(model=1, c=0.7),
+])
+def test_threshold_table_equals_oracle(kw):
+    p = S.Params(**kw)
+    np.testing.assert_array_equal(S.threshold_table(p), O.threshold_table(oracle_params(p)))
+
+
+def test_record_observables():
+    p = S.Params(L=8, J=1.5, h=0.25)
+    recs = np.zeros(2, dtype=S.RECORD_DTYPE)
+    recs["bond_sum"] = [100, -20]
+    recs["mag"] = [10, -4]
+    E, M, P = np.zeros(2), np.zeros(2), np.zeros(2)
+    assert S.lib().sl_record_observables(ctypes.byref(p.c_struct()), recs.ctypes.data, 2,
+                                         E.ctypes.data, M.ctypes.data, P.ctypes.data) == 0
+    np.testing.assert_array_equal(E, [-1.5 * 100 - 0.25 * 10, -1.5 * -20 - 0.25 * -4])
+    np.testing.assert_array_equal(M, [10, -4])
+    assert np.all(np.isnan(P))
+    q = S.Params(model=1, L=8, c=0.2)
+    recs["unflipped"] = [64, 16]
+    assert S.lib().sl_record_observables(ctypes.byref(q.c_struct()), recs.ctypes.data, 2,
+                                         E.ctypes.data, M.ctypes.data, P.ctypes.data) == 0
+    np.testing.assert_array_equal(P, [1.0, 0.25])
+
+
+def test_status_strings():
+    for code, name in B.STATUS.items():
+        assert S.lib().sl_status_str(code).decode() == name
