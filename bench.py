@@ -1,0 +1,157 @@
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+A step is one full sweep (colour 0 then colour 1, with the fused per-sweep
+reduction of bond sum, magnetisation and accepted moves) of the 2D spin-1/2
+Ising lattice L = 8192, J = 1, h = 0, T = 2.269, random start from seed 1;
+the records of the timed sweeps are drained (measure) inside the timed
+region.  The lattice is created and warmed up before timing, so it is
+resident in HBM when the timed region starts.
+
+Printed: one JSON line with flip attempts/s, the roofline position of the
+sweep kernel (2 algorithmic bytes per attempt: every int8 site read and
+written once per sweep), the same for the 3D L = 256 lattice, and the CPU
+oracle's rate on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
+
+
+def _lattice(S, cfg, T=None, record_capacity=4096):
+    p = S.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
+                 J=cfg.get("J", 1.0), h=cfg.get("h", 0.0), T=T if T is not None else cfg.get("T", 1.0),
+                 c=cfg.get("c", 0.1), seed=cfg["seed"], init=cfg["init"],
+                 record_capacity=record_capacity)
+    return p, S.Lattice(p)
+
+
+def time_workload(S, torch, name, cfg, steps, warmup, T=None):
+    """Warm up, then time `steps` sweeps plus the drain of their records."""
+    p, lat = _lattice(S, cfg, T=T, record_capacity=max(steps, warmup) + 2)
+    lat.sweep(warmup)
+    lat.measure()
+    stream = lat.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    lat.sweep(steps)
+    end.record(stream)
+    recs = lat.measure()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms = start.elapsed_time(end)  # the sweep launches only, on their stream
+    assert len(recs) == steps
+    mode = lat.get_launch()
+    lat.close()
+    attempts = p.nsites * steps
+    launches_per_sweep = 1 if mode[0] == S.MODE_FUSED else 2
+    per_launch_s = sweep_ms / 1e3 / (steps * launches_per_sweep)
+    bytes_per_launch = ALGO_BYTES_PER_ATTEMPT * p.nsites / launches_per_sweep
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    return {
+        "workload": name, "attempts_per_s": attempts / wall, "wall_s": wall,
+        "ms_per_step": wall * 1e3 / steps, "sweep_kernels_ms_per_step": sweep_ms / steps,
+        "launch": {"mode": mode[0], "tile_rows": mode[1], "tile_words": mode[2],
+                   "launches_per_sweep": launches_per_sweep},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "per_launch_us": per_launch_s * 1e6, "algo_bytes_per_launch": bytes_per_launch},
+        "nsites": p.nsites, "steps": steps,
+    }
+
+
+def cpu_baseline(cfg, sweeps, threads):
+    """The oracle as it is, on the host cores, on `sweeps` sweeps of the same lattice."""
+    import oracle as O
+
+    p = O.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
+                 init=O.INIT_COLD if cfg["init"] == 0 else O.INIT_RANDOM, J=cfg.get("J", 1.0),
+                 h=cfg.get("h", 0.0), T=cfg.get("T", 1.0), c=cfg.get("c", 0.1), seed=cfg["seed"])
+    s = O.init_lattice(p)
+    t0 = time.perf_counter()
+    O.run(p, s, 0, sweeps, records=True, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": p.nsites * sweeps / dt, "unit": "flip attempts/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sweeps} sweeps of 2D L={cfg['L']} (records every sweep), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 3D L=256 line")
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU slab decomposition is a design, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1209_0296_amd as S
+    from workloads import CONFIGS
+
+    torch.cuda.set_device(0)
+    cfg2 = CONFIGS["ising2d_L8192"]
+    main_res = time_workload(S, torch, "ising2d_L8192_T2.269", cfg2, args.steps, args.warmup)
+    print(f"# 2D L=8192: {main_res['attempts_per_s']:.4g} attempts/s, "
+          f"{main_res['ms_per_step']:.4f} ms/sweep", file=sys.stderr, flush=True)
+    secondary = []
+    if not args.no_secondary:
+        for key in ("ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096"):
+            r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
+            print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
+                  file=sys.stderr, flush=True)
+            secondary.append({k: r[k] for k in ("workload", "attempts_per_s", "ms_per_step",
+                                                 "sweep_kernels_ms_per_step", "launch")}
+                             | {"roofline_frac": r["roofline"]["frac"]})
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(cfg2, args.cpu_sweeps, threads)
+        print(f"# oracle: {cpu['value']:.4g} attempts/s on {threads} threads", file=sys.stderr,
+              flush=True)
+
+    roof = dict(main_res["roofline"])
+    line = {
+        "metric": "flip attempts/s at 2D L=8192 (% HBM peak)",
+        "value": main_res["attempts_per_s"],
+        "unit": "flip attempts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "ising2d_L8192_T2.269", "dim": 2, "L": 8192, "spin": "1/2",
+                   "J": 1.0, "h": 0.0, "T": 2.269, "start": "random", "seed": 1,
+                   "spins": "int8", "launch": main_res["launch"]},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_detail": {"per_launch_us": roof["per_launch_us"],
+                            "algo_bytes_per_launch": roof["algo_bytes_per_launch"],
+                            "algo_bytes_per_attempt": ALGO_BYTES_PER_ATTEMPT},
+        "cpu_baseline": cpu,
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

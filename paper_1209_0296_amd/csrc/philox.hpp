@@ -33,7 +33,21 @@ struct Words4 {
     uint32_t w[4];
 };
 
-// Counter (c0, c1, c2, c3) -> four uniform 32-bit words.
+// a ^ b ^ c in one VALU instruction (gfx950 three-input bitwise op, truth
+// table 0x96).  The third operand is wave-uniform (a round key) and stays in
+// a scalar register.  Not volatile: the compiler may schedule or drop it.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+// Counter (c0, c1, c2, c3) -> four uniform 32-bit words.  Rounds 0 and 1 are
+// left to the compiler: when counter words 1-3 are uniform across the wave
+// (colour, sweep, tag) it evaluates their products on the scalar unit.  From
+// round 2 on every word varies per lane and each round is two 32x32->64
+// multiply-adds and two three-way xors.
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                 uint32_t c3, const PhiloxKey& ks)
 {
@@ -41,8 +55,14 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ ks.k0[r];
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ ks.k1[r];
+        uint32_t n0, n2;
+        if (r < 2) {
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ ks.k0[r];
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ ks.k1[r];
+        } else {
+            n0 = xor3((uint32_t)(p1 >> 32), c1, ks.k0[r]);
+            n2 = xor3((uint32_t)(p0 >> 32), c3, ks.k1[r]);
+        }
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -44,7 +44,8 @@ struct Layout {
     uint64_t nsites;   // L^dim
     uint64_t nh;       // per colour
     size_t col_bytes;  // one colour array, rounded to kAlign
-    size_t off_col1;
+    size_t off_col[2][2];  // [copy][colour]: two copies of the lattice (fused sweeps
+                           // read one and write the other)
     size_t off_acc;    // accumulators [capacity][kSub][kQ] int64
     size_t off_out;    // folded records [capacity][5] int64
     size_t off_lut;    // threshold table, kMaxLut u64
@@ -105,8 +106,9 @@ Layout layout_of(const sl_params* p)
     l.nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
     l.nh = l.nsites / 2;
     l.col_bytes = round_up(l.nh, kAlign);
-    l.off_col1 = l.col_bytes;
-    l.off_acc = 2 * l.col_bytes;
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) l.off_col[b][c] = (size_t)(2 * b + c) * l.col_bytes;
+    l.off_acc = 4 * l.col_bytes;
     l.off_out = l.off_acc + round_up(p->record_capacity * kSlotWords * sizeof(int64_t), kAlign);
     l.off_lut = l.off_out + round_up(p->record_capacity * kRecordWords * sizeof(int64_t), kAlign);
     l.total = l.off_lut + round_up(kMaxLut * sizeof(uint64_t), kAlign);
@@ -157,6 +159,7 @@ struct sl_lattice {
     uint64_t next_t;   // index of the next sweep
     uint64_t pending;  // unread records
     uint64_t first_t;  // t of the oldest unread record
+    int cur;           // copy of the lattice holding the current state
     sl_launch launch;
     uint64_t table[kMaxLut];
     size_t table_n;
@@ -167,8 +170,8 @@ namespace {
 SweepArgs args_of(const sl_lattice* h)
 {
     SweepArgs a{};
-    a.col[0] = h->base;
-    a.col[1] = h->base + h->lay.off_col1;
+    a.col[0] = h->base + h->lay.off_col[h->cur][0];
+    a.col[1] = h->base + h->lay.off_col[h->cur][1];
     a.g.L = (uint32_t)h->params.L;
     a.g.Lh = (uint32_t)(h->params.L / 2);
     a.g.dim = (uint32_t)h->params.dim;
@@ -189,14 +192,15 @@ unsigned long long* slot_ptr(const sl_lattice* h, uint64_t idx)
     return reinterpret_cast<unsigned long long*>(h->base + h->lay.off_acc) + idx * kSlotWords;
 }
 
-// Default schedule for a shape.
+// Default schedule for a shape: 2D lattices take one fused launch per sweep,
+// 3D lattices two in-place half-sweeps (a fused 3D sweep would recompute a
+// halo in two directions).
 sl_launch auto_launch(const sl_lattice* h)
 {
     sl_launch l{};
-    l.mode = SL_MODE_SIMPLE;
+    l.mode = h->params.dim == 2 ? SL_MODE_FUSED : SL_MODE_HALF;
     l.tile_rows = 0;
     l.tile_words = 0;
-    (void)h;
     return l;
 }
 
@@ -277,6 +281,7 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
     h->next_t = params->t0;
     h->pending = 0;
     h->first_t = params->t0;
+    h->cur = 0;
     h->table_n = build_table(params, h->table);
     h->launch = auto_launch(h);
 
@@ -350,9 +355,18 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
         a.acc = slot_ptr(h, h->pending + i);
         hipError_t e = hipSuccess;
         switch (h->launch.mode) {
-            case SL_MODE_FUSED:
-                e = launch_fused_sweep(a, h->kind, h->stream);
+            case SL_MODE_FUSED: {
+                const int nxt = h->cur ^ 1;
+                uint8_t* d0 = h->base + h->lay.off_col[nxt][0];
+                uint8_t* d1 = h->base + h->lay.off_col[nxt][1];
+                e = launch_fused_sweep(a, h->kind, a.col[0], a.col[1], d0, d1, h->stream);
+                if (e == hipSuccess) {
+                    h->cur = nxt;
+                    a.col[0] = d0;
+                    a.col[1] = d1;
+                }
                 break;
+            }
             case SL_MODE_HALF:
                 for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
                     a.colour = c;

@@ -50,11 +50,12 @@ hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s);
 hipError_t launch_clear_flags(const SweepArgs& a, hipStream_t s);
 hipError_t launch_simple_half(const SweepArgs& a, int kind, hipStream_t s);
 hipError_t launch_tiled_half(const SweepArgs& a, int kind, hipStream_t s);
-hipError_t launch_fused_sweep(const SweepArgs& a, int kind, hipStream_t s);
+hipError_t launch_fused_sweep(const SweepArgs& a, int kind, const uint8_t* src0, const uint8_t* src1,
+                              uint8_t* dst0, uint8_t* dst1, hipStream_t s);
 hipError_t launch_fold(unsigned long long* acc, int64_t* out, uint64_t n, uint64_t t_first,
                        int ising, hipStream_t s);
 
-// Shape limits of the tiled kernels (checked by the runtime before launch).
+// Shape limits of the streaming kernels (checked by the runtime before launch).
 bool tiled_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused);
 
 }  // namespace spinlat

@@ -1,5 +1,7 @@
-"""GPU parity: the HIP sweep must reproduce the oracle's lattice and every
-per-sweep record bit for bit (integer result: exact equality)."""
+"""GPU parity: every launch schedule of the HIP sweep must reproduce the
+oracle's lattice and every per-sweep record bit for bit (integer result:
+exact equality), on small lattices spanning several windows, strips and a
+ragged tail, at the benchmarked sizes, and across split runs and restarts."""
 import numpy as np
 import pytest
 
@@ -9,41 +11,211 @@ from helpers import run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 
 SIMPLE = (S.MODE_SIMPLE, 0, 0)
+HALF = (S.MODE_HALF, 0, 0)
+FUSED = (S.MODE_FUSED, 0, 0)
+AUTO = (S.MODE_AUTO, 0, 0)
 
 
-def _check(sp, nsweeps, launch=None, chunks=None):
+def _check(sp, nsweeps, launch=None, chunks=None, nthreads=0):
     print(f"case model={sp.model} dim={sp.dim} L={sp.L} two_s={sp.two_s} T={sp.T} c={sp.c} "
-          f"n={nsweeps} launch={launch}", flush=True)
+          f"n={nsweeps} launch={launch} chunks={chunks}", flush=True)
     g_s, g_r = run_gpu(sp, nsweeps, launch=launch, chunks=chunks)
-    o_s, o_r = run_oracle(sp, nsweeps)
+    o_s, o_r = run_oracle(sp, nsweeps, nthreads=nthreads)
     assert g_r.shape == o_r.shape
     np.testing.assert_array_equal(g_r, o_r)
     np.testing.assert_array_equal(g_s, o_s)
 
 
-def test_ising2d_L64_cold_1000_sweeps():
+@pytest.mark.parametrize("launch", [SIMPLE, HALF, FUSED, AUTO])
+def test_ising2d_L64_cold_1000_sweeps(launch):
     """64x64, J=1, T=2.269, cold start, seed 1, 1000 sweeps, every record."""
     sp = S.Params(L=64, T=2.269, init=S.INIT_COLD, seed=1, record_capacity=1001)
-    _check(sp, 1000, launch=SIMPLE)
+    _check(sp, 1000, launch=launch)
 
 
-@pytest.mark.parametrize("L", [8, 16, 40, 64])
+# L = 8, 16, 64: one group covers a row; 40, 72, 136: windows with wrapped
+# columns; 512: exactly 64 columns; 1040: three windows with a ragged tail
+SHAPES_2D = [8, 16, 40, 64, 72, 136, 512, 1040]
+
+
+@pytest.mark.parametrize("L", SHAPES_2D)
 @pytest.mark.parametrize("two_s", [1, 2])
-def test_ising2d_small(L, two_s):
+@pytest.mark.parametrize("launch", [SIMPLE, HALF, FUSED])
+def test_ising2d_shapes(L, two_s, launch):
+    n = 12 if L >= 512 else 25
     sp = S.Params(L=L, two_s=two_s, T=2.0 if two_s == 1 else 1.5, seed=7 + L, record_capacity=64)
-    _check(sp, 30, launch=SIMPLE)
+    _check(sp, n, launch=launch)
 
 
-@pytest.mark.parametrize("L", [8, 16, 24])
+@pytest.mark.parametrize("rows", [1, 2, 3, 7, 16, 33])
+@pytest.mark.parametrize("mode", [S.MODE_HALF, S.MODE_FUSED])
+def test_strip_heights(rows, mode):
+    sp = S.Params(L=136, T=2.269, seed=5, record_capacity=64)
+    _check(sp, 10, launch=(mode, rows, 0))
+
+
+@pytest.mark.parametrize("L", [8, 16, 24, 40, 64])
 @pytest.mark.parametrize("two_s", [1, 2])
-def test_ising3d_small(L, two_s):
+@pytest.mark.parametrize("launch", [SIMPLE, HALF, (S.MODE_HALF, 5, 0)])
+def test_ising3d_shapes(L, two_s, launch):
     sp = S.Params(dim=3, L=L, two_s=two_s, T=4.5 if two_s == 1 else 3.2, seed=3 + L,
                   record_capacity=64)
-    _check(sp, 20, launch=SIMPLE)
+    _check(sp, 12, launch=launch)
 
 
-@pytest.mark.parametrize("L", [8, 32, 72])
+@pytest.mark.parametrize("L", [8, 32, 72, 1040])
 @pytest.mark.parametrize("c", [0.05, 0.2, 0.6])
-def test_ne_small(L, c):
+@pytest.mark.parametrize("launch", [SIMPLE, HALF, FUSED])
+def test_ne_shapes(L, c, launch):
     sp = S.Params(model=S.NORTH_EAST, L=L, c=c, seed=11, record_capacity=64)
-    _check(sp, 40, launch=SIMPLE)
+    _check(sp, 12 if L > 512 else 30, launch=launch)
+
+
+def test_fields_and_couplings():
+    for kw in (dict(T=1.3, h=0.37), dict(T=2.1, J=-1.0, h=0.2), dict(two_s=2, T=1.1, h=-0.3),
+               dict(dim=3, T=3.0, h=0.5), dict(dim=3, two_s=2, T=2.0, J=0.7, h=-0.2)):
+        for launch in (HALF, FUSED) if kw.get("dim", 2) == 2 else (HALF,):
+            sp = S.Params(L=40, seed=13, record_capacity=64, **kw)
+            _check(sp, 10, launch=launch)
+
+
+def test_infinite_temperature_flips_everything():
+    sp = S.Params(L=64, T=float("inf"), seed=2, record_capacity=8)
+    for launch in (SIMPLE, HALF, FUSED):
+        g_s, g_r = run_gpu(sp, 2, launch=launch)
+        o_s, o_r = run_oracle(sp, 2)
+        np.testing.assert_array_equal(g_s, o_s)
+        np.testing.assert_array_equal(g_r, o_r)
+        assert np.all(g_r[1:, 3] == sp.nsites)
+
+
+def test_split_runs_and_mixed_schedules():
+    """sweep(a) + sweep(b) + ... with different schedules == one run."""
+    import torch
+
+    sp = S.Params(L=136, T=2.269, seed=21, record_capacity=64)
+    lat = S.Lattice(sp)
+    recs = [S.records_to_array(lat.measure())]
+    for launch, n in ((SIMPLE, 3), (FUSED, 4), (HALF, 2), ((S.MODE_FUSED, 5, 0), 5), (HALF, 1)):
+        lat.set_launch(*launch)
+        lat.sweep(n)
+        if n > 2:
+            recs.append(S.records_to_array(lat.measure()))
+    recs.append(S.records_to_array(lat.measure()))
+    g_s = lat.spins()
+    lat.close()
+    o_s, o_r = run_oracle(sp, 15)
+    np.testing.assert_array_equal(np.vstack(recs), o_r)
+    np.testing.assert_array_equal(g_s, o_s)
+
+
+@pytest.mark.parametrize("model,dim,two_s", [(0, 2, 1), (0, 3, 2), (1, 2, 1)])
+def test_checkpoint_restart(model, dim, two_s):
+    """copy_spins at sweep a, recreate from that buffer with t0 = a, continue:
+    identical to the uninterrupted run (the random numbers carry no state)."""
+    L = 40 if dim == 3 else 72
+    base = dict(model=model, dim=dim, L=L, two_s=two_s, T=2.5, c=0.3, seed=17, record_capacity=64)
+    sp = S.Params(**base)
+    lat = S.Lattice(sp)
+    lat.sweep(7)
+    lat.measure()
+    snap = lat.copy_spins().clone()
+    lat.close()
+    sp2 = S.Params(**base, init=S.INIT_BUFFER, t0=7)
+    lat2 = S.Lattice(sp2, init_spins=snap)
+    r0 = S.records_to_array(lat2.measure())
+    lat2.sweep(5)
+    r = S.records_to_array(lat2.measure())
+    g_s = lat2.spins()
+    lat2.close()
+    o_s, o_r = run_oracle(sp, 12)
+    np.testing.assert_array_equal(g_s, o_s)
+    np.testing.assert_array_equal(r, o_r[8:])
+    assert r0[0, 0] == 7
+    np.testing.assert_array_equal(r0[0, 1:3], o_r[7, 1:3])
+
+
+def test_buffer_init_roundtrip():
+    import torch
+    from workloads import random_lattice
+
+    for kw in (dict(L=64), dict(L=40, two_s=2), dict(dim=3, L=16), dict(model=1, L=64, c=0.3)):
+        sp = S.Params(init=S.INIT_BUFFER, seed=3, record_capacity=8, **kw)
+        start = random_lattice(sp.shape, two_s=sp.two_s, seed=5, model=sp.model,
+                               flag_fraction=0.3)
+        lat = S.Lattice(sp, init_spins=torch.from_numpy(start))
+        np.testing.assert_array_equal(lat.spins(), start)
+        lat.sweep(3)
+        recs = S.records_to_array(lat.measure())
+        g = lat.spins()
+        lat.close()
+        o_s, o_r = run_oracle(sp, 3, start=start)
+        np.testing.assert_array_equal(g, o_s)
+        np.testing.assert_array_equal(recs, o_r)
+
+
+def test_ne_persistence_reset():
+    sp = S.Params(model=S.NORTH_EAST, L=64, c=0.2, seed=4, record_capacity=64)
+    lat = S.Lattice(sp)
+    lat.sweep(10)
+    r1 = S.records_to_array(lat.measure())
+    lat.reset_persistence()
+    lat.sweep(5)
+    r2 = S.records_to_array(lat.measure())
+    spins = lat.spins()
+    lat.close()
+    assert np.all(np.diff(r1[:, 4]) <= 0) and r1[0, 4] == sp.nsites
+    assert np.all(np.diff(r2[:, 4]) <= 0)
+    import oracle as O
+    from helpers import oracle_params
+
+    op = oracle_params(sp)
+    s = O.init_lattice(op)
+    O.run(op, s, 0, 10, records=False)
+    O.reset_persistence(op, s)
+    rec = O.run(op, s, 10, 5)
+    np.testing.assert_array_equal(r2, rec)
+    np.testing.assert_array_equal(spins, s)
+
+
+def test_record_ring_errors():
+    sp = S.Params(L=64, record_capacity=4)
+    lat = S.Lattice(sp)
+    lat.sweep(3)
+    with pytest.raises(S.SpinlatError) as e:
+        lat.sweep(1)
+    assert e.value.status == 5
+    recs = lat.measure()
+    assert len(recs) == 4 and list(recs["t"]) == [0, 1, 2, 3]
+    lat.sweep(4)
+    assert len(lat.measure()) == 4
+    lat.close()
+    sp = S.Params(L=64, t0=2 ** 32 - 2, record_capacity=8)
+    lat = S.Lattice(sp)
+    lat.sweep(2)
+    with pytest.raises(S.SpinlatError) as e:
+        lat.sweep(1)
+    assert e.value.status == 6
+    lat.close()
+
+
+# ---------------------------------------------------------------------------
+# Benchmarked sizes, in the schedule bench.py times (AUTO), against the oracle
+# on all host threads: the whole lattice and every record.
+
+@pytest.mark.parametrize("name,nsweeps", [("ising2d_L8192", 3), ("ising3d_L256_s12", 4),
+                                          ("ising3d_L256_s1", 3), ("ne2d_L4096", 6)])
+def test_benchmarked_sizes(name, nsweeps):
+    from workloads import CONFIGS
+
+    cfg = CONFIGS[name]
+    sp = S.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
+                  T=cfg.get("T", 1.0), c=cfg.get("c", 0.1), seed=cfg["seed"], init=cfg["init"],
+                  record_capacity=16)
+    _check(sp, nsweeps, launch=AUTO, nthreads=16)
+
+
+@pytest.mark.parametrize("T", [2.0, 2.6])
+def test_ising2d_L8192_other_temperatures(T):
+    sp = S.Params(L=8192, T=T, seed=1, record_capacity=8)
+    _check(sp, 2, launch=AUTO, nthreads=16)
