@@ -104,18 +104,22 @@ typedef struct sl_record {
 
 /* Launch schedule.  Every schedule produces the same lattice and records. */
 typedef enum sl_mode {
-    SL_MODE_AUTO = 0,   /* library's choice for the shape */
-    SL_MODE_SIMPLE = 1, /* one thread per 4 same-colour sites, direct global loads,
-                           two launches per sweep */
-    SL_MODE_HALF = 2,   /* LDS tile + halo per workgroup, two launches per sweep */
-    SL_MODE_FUSED = 3   /* LDS tile with a 2-deep halo: both colours in one launch,
-                           colour-0 halo updates recomputed (2D only) */
+    SL_MODE_AUTO = 0,         /* library's choice for the shape */
+    SL_MODE_SIMPLE = 1,       /* one thread per 4 same-colour sites, direct global loads,
+                                 two launches per sweep */
+    SL_MODE_HALF = 2,         /* row-group streaming, one colour in place per launch,
+                                 two launches per sweep (2D and 3D) */
+    SL_MODE_FUSED = 3,        /* row-group streaming, both colours in one launch per sweep
+                                 with the colour-0 halo rows recomputed (2D only) */
+    SL_MODE_HALF_WINDOW = 4,  /* as HALF with 64-lane column windows (any shape) */
+    SL_MODE_FUSED_WINDOW = 5  /* as FUSED with 64-lane column windows and halo lanes */
 } sl_mode;
 
 typedef struct sl_launch {
     int32_t mode;        /* sl_mode */
-    int32_t tile_rows;   /* LDS modes: rows of the tile (2D: y; 3D: y and z each) */
-    int32_t tile_words;  /* LDS modes: 4-byte words of one colour row per tile */
+    int32_t tile_rows;   /* streaming modes: rows per strip (0: default) */
+    int32_t tile_words;  /* HALF/FUSED: 4-byte words per lane, 1, 2 or 4 (0: default);
+                            must be 0 for the window modes */
     int32_t reserved;
 } sl_launch;
 
@@ -136,7 +140,9 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
                             void* hip_stream, sl_lattice** out);
 
 /* Choose the launch schedule for later sweeps (validated; SL_E_UNSUPPORTED if
- * the schedule does not fit the shape). */
+ * the schedule does not fit the shape: HALF/FUSED need the colour row to split
+ * into row groups of <= 64 lanes or a multiple of 64 lanes up to 1024, and for
+ * spin-1/2 every threshold >= 1; the window modes take any shape). */
 sl_status sl_set_launch(sl_lattice* lat, const sl_launch* launch);
 sl_status sl_get_launch(const sl_lattice* lat, sl_launch* launch);
 

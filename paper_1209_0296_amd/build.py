@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspinlat.so")
-SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "runtime.cpp"]
+SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "kernels_row.hip", "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,672 @@
+// kernels_row.hip -- whole-row streaming checkerboard kernels for gfx950.
+//
+// A row group of R lanes covers one whole colour row (ncols = L/8 four-byte
+// words): each lane holds D consecutive words (D*4 same-colour sites) and
+// loads them with one 4*D-byte access.  Because the group spans the row, the
+// periodic same-row neighbours never leave it: inside a lane they come from
+// the lane's own words, across lanes from a lane shift (DPP within a wave,
+// LDS between the waves of a group when R > 64).  The group walks down a
+// strip of rows keeping the other colour's rows y-1, y, y+1 in registers and
+// prefetching the next row's words while it computes the current one.
+//
+// HALF (2D and 3D): one colour in place per launch (reads only the other
+// colour and its own words), two launches per sweep.
+// FUSED (2D): both colours of a strip per launch; the colour-0 rows just
+// above and below the strip are recomputed (bit-identical, counter-based
+// random numbers) and the sweep reads one copy of the lattice and writes the
+// other, since neighbouring strips read those rows.
+//
+// Spin-1/2 acceptance uses a 32-bit table of thr-1 (requires every threshold
+// >= 1; the runtime sends other tables to the generic kernels).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+#include "site_update.hpp"
+#include "spinlat_internal.h"
+
+namespace spinlat {
+
+namespace {
+
+constexpr uint32_t M4 = 0x04040404u;
+
+struct RowGeom {
+    uint32_t L, Lh, ncols;
+    uint32_t D;       // words per lane
+    uint32_t R;       // lanes per row group
+    uint32_t slots;   // row groups per wave (R <= 64)
+    uint32_t nw;      // waves per row group (R > 64)
+    uint32_t nplanes, H, nstrips, nitems;
+    uint32_t block;   // threads per block
+};
+
+__host__ __device__ inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+__device__ __forceinline__ uint32_t wrapr(int y, uint32_t L)
+{
+    int r = y % (int)L;
+    return (uint32_t)(r < 0 ? r + (int)L : r);
+}
+
+__device__ __forceinline__ uint32_t remap_block()
+{
+    const uint32_t nb = gridDim.x;
+    uint32_t b = blockIdx.x;
+    if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
+    return b;
+}
+
+template <int D>
+struct Vec {
+    uint32_t w[D];
+};
+
+template <int D>
+__device__ __forceinline__ Vec<D> ldv(const uint8_t* base, uint64_t off)
+{
+    Vec<D> v;
+    if constexpr (D == 4) {
+        const uint4 q = *reinterpret_cast<const uint4*>(base + off);
+        v.w[0] = q.x; v.w[1] = q.y; v.w[2] = q.z; v.w[3] = q.w;
+    } else if constexpr (D == 2) {
+        const uint2 q = *reinterpret_cast<const uint2*>(base + off);
+        v.w[0] = q.x; v.w[1] = q.y;
+    } else {
+        v.w[0] = *reinterpret_cast<const uint32_t*>(base + off);
+    }
+    return v;
+}
+
+template <int D>
+__device__ __forceinline__ void stv(uint8_t* base, uint64_t off, const Vec<D>& v)
+{
+    if constexpr (D == 4) {
+        *reinterpret_cast<uint4*>(base + off) = make_uint4(v.w[0], v.w[1], v.w[2], v.w[3]);
+    } else if constexpr (D == 2) {
+        *reinterpret_cast<uint2*>(base + off) = make_uint2(v.w[0], v.w[1]);
+    } else {
+        *reinterpret_cast<uint32_t*>(base + off) = v.w[0];
+    }
+}
+
+// Cross-lane neighbour word.  For row parity p = 0 a lane needs the last word
+// of the lane to its left, for p = 1 the first word of the lane to its right
+// (periodic within the row group).
+struct Lanes {
+    uint32_t lane, wave, pos, src_l, src_r;
+};
+
+template <bool XW>
+__device__ __forceinline__ uint32_t shift_in(uint32_t last, uint32_t first, uint32_t p, const Lanes& ln,
+                                             uint32_t e)
+{
+    // e: value the wave-edge lane takes (from LDS) when XW
+    if constexpr (XW) {
+        if (p == 0) return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)last, 0x138, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)first, 0x130, 0xF, 0xF, false);
+    } else {
+        return (uint32_t)__shfl((int)(p ? first : last), (int)(p ? ln.src_r : ln.src_l), 64);
+    }
+}
+
+// Aligned neighbour words of the D words of a lane in the same row.
+template <int D>
+__device__ __forceinline__ void side_words(const Vec<D>& o, uint32_t x, uint32_t p, uint32_t (&s)[D])
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (p == 0) {
+            const uint32_t prev = d > 0 ? o.w[d > 0 ? d - 1 : 0] : x;
+            s[d] = __builtin_amdgcn_alignbyte(o.w[d], prev, 3);
+        } else {
+            const uint32_t next = d < D - 1 ? o.w[d < D - 1 ? d + 1 : 0] : x;
+            s[d] = __builtin_amdgcn_alignbyte(next, o.w[d], 1);
+        }
+    }
+}
+
+// ---- tables ---------------------------------------------------------------
+struct RowLuts {
+    uint64_t e[3 * 2 * 13];  // spin-1 entries; spin-1/2 uses the first words as u32
+};
+
+template <int KIND, int DIM>
+__device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* table, uint64_t& thr_up,
+                                               uint64_t& thr_down)
+{
+    constexpr int z = 2 * DIM;
+    for (int t = threadIdx.x; t < 6 * (2 * z + 1); t += blockDim.x) {
+        if (KIND == KIND_ISING_HALF) {
+            if (t < 2 * (z + 1)) {
+                const int sneg = t / (z + 1), m = t % (z + 1);
+                const int s = sneg ? -1 : 1;
+                const int nsum = s * (z - 2 * m);
+                const int di = s > 0 ? 0 : 3;
+                // thr >= 1 here: accept iff word <= thr - 1
+                reinterpret_cast<uint32_t*>(lut.e)[t] =
+                    (uint32_t)(table[di * (2 * z + 1) + nsum + z] - 1ull);
+            }
+        } else if (KIND == KIND_ISING_ONE) {
+            const int nz = t % (2 * z + 1);
+            const int ch = (t / (2 * z + 1)) & 1;
+            const int s = t / (2 * (2 * z + 1)) - 1;
+            const int av = (s == -1) ? 0 : -1;
+            const int bv = (s == 1) ? 0 : 1;
+            const int sp = ch ? bv : av;
+            const uint64_t thr = table[ds_index(sp - s) * (2 * z + 1) + nz];
+            lut.e[t] = thr | ((uint64_t)(uint32_t)(sp + 1) << 40);
+        }
+    }
+    thr_up = table[0];
+    thr_down = table[1];
+}
+
+struct Obs {
+    int32_t bond, mag, acc, unfl;
+};
+
+// ---- one word -----------------------------------------------------------------
+// nb: [same, side, y-1, y+1, (z-1, z+1)] aligned to the word's four sites.
+template <int DIM>
+__device__ __forceinline__ uint32_t half_word(uint32_t own, const uint32_t (&nb)[2 * DIM], const Words4& w,
+                                              const uint8_t* lut_bytes)
+{
+    constexpr int z = 2 * DIM;
+    uint32_t mis = 0;
+#pragma unroll
+    for (int j = 0; j < z; ++j) mis += (nb[j] ^ own) & M4;  // 4 per anti-aligned neighbour
+    const uint32_t idx4 = mis + (own & M4) * (uint32_t)(z + 1);
+    uint32_t flip = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t off = (idx4 >> (8 * b)) & 0xFFu;
+        const uint32_t t = *reinterpret_cast<const uint32_t*>(lut_bytes + off);
+        flip |= (w.w[b] <= t) ? (0xFEu << (8 * b)) : 0u;
+    }
+    return own ^ flip;
+}
+
+template <int DIM>
+__device__ __forceinline__ void half_obs(uint32_t own, uint32_t nw, const uint32_t (&nb)[2 * DIM], bool bond,
+                                         Obs& o)
+{
+    constexpr int z = 2 * DIM;
+    o.acc += __builtin_popcount(own ^ nw);         // 7 per flip
+    o.mag += __builtin_popcount(nw & 0x02020202u);  // number of -1 spins
+    if (bond) {
+        uint32_t mis = 0;
+#pragma unroll
+        for (int j = 0; j < z; ++j) mis += (nb[j] ^ nw) & M4;
+        o.bond += (int)__builtin_amdgcn_sad_u8(mis, 0u, 0u);  // 4 * anti-aligned bonds
+    }
+}
+
+__device__ __forceinline__ uint32_t bias1(uint32_t v) { return (v ^ 0x80808080u) + 0x80808081u; }
+
+template <int DIM>
+__device__ __forceinline__ uint32_t one_word(uint32_t own, const uint32_t (&nb)[2 * DIM], const Words4& wa,
+                                             const Words4& wb, const RowLuts& lut, bool count, bool bond,
+                                             Obs& o)
+{
+    constexpr int z = 2 * DIM;
+    uint32_t S = 0;
+#pragma unroll
+    for (int j = 0; j < z; ++j) S += bias1(nb[j]);
+    const uint32_t ob = bias1(own);
+    uint32_t out = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const Words4& w = b < 2 ? wa : wb;
+        const uint32_t ua = w.w[(b & 1) * 2];
+        const uint32_t up = w.w[(b & 1) * 2 + 1];
+        const uint32_t s1 = (ob >> (8 * b)) & 0xFFu;
+        const uint32_t nz = (S >> (8 * b)) & 0xFFu;
+        const uint64_t ent = lut.e[(s1 * 2 + (up >> 31)) * (2 * z + 1) + nz];
+        const uint32_t n1 = ((uint64_t)ua < (ent & 0x1FFFFFFFFull)) ? (uint32_t)(ent >> 40) : s1;
+        out |= ((n1 - 1u) & 0xFFu) << (8 * b);
+        if (count) {
+            o.acc += n1 != s1;
+            o.mag += (int)n1 - 1;
+            if (bond) o.bond += ((int)n1 - 1) * ((int)nz - z);
+        }
+    }
+    return out;
+}
+
+__device__ __forceinline__ uint32_t ne_word(uint32_t own, uint32_t north, uint32_t east, uint32_t g,
+                                            uint32_t colour, uint32_t t, const PhiloxKey& ks,
+                                            uint64_t thr_up, uint64_t thr_down)
+{
+    const uint32_t n = own & 0x01010101u;
+    const uint32_t allowed = north & east & 0x01010101u;
+    const uint32_t up = allowed & ~n;
+    const uint32_t down = allowed & n;
+    const bool up_rand = thr_up < (1ull << 32);
+    const bool down_rand = thr_down < (1ull << 32);
+    const uint32_t need = (up_rand ? up : 0u) | (down_rand ? down : 0u);
+    uint32_t f = (up_rand ? 0u : up) | (down_rand ? 0u : down);
+    if (__builtin_amdgcn_ballot_w64(need != 0u) != 0ull) {
+        const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t bit = 1u << (8 * b);
+            const uint32_t thr = (uint32_t)((n & bit) ? thr_down : thr_up);
+            if ((need & bit) && w.w[b] < thr) f |= bit;
+        }
+    }
+    return (own ^ f) | (f << 1);
+}
+
+__device__ __forceinline__ void ne_obs(uint32_t own, uint32_t nw, uint32_t north, uint32_t south,
+                                       uint32_t east, uint32_t west, bool bond, Obs& o)
+{
+    o.acc += __builtin_popcount((own ^ nw) & 0x01010101u);
+    o.mag += __builtin_popcount(nw & 0x01010101u);
+    o.unfl += 4 - __builtin_popcount(nw & 0x02020202u);
+    if (bond) {
+        const uint32_t m = 0x01010101u;
+        const uint32_t s = (north & m) + (south & m) + (east & m) + (west & m);
+        o.bond += (int)__builtin_amdgcn_sad_u8(s & ((nw & m) * 0xFFu), 0u, 0u);
+    }
+}
+
+// Update the D words of one lane in one row.  g0 = Philox group of word 0.
+template <int KIND, int DIM, int D>
+__device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& same, const uint32_t (&side)[D],
+                                             const Vec<D>& up, const Vec<D>& down, const Vec<D>* zm,
+                                             const Vec<D>* zp, uint32_t p, uint32_t g0, uint32_t colour,
+                                             uint32_t t, const PhiloxKey& ks, const RowLuts& lut,
+                                             uint64_t thr_up, uint64_t thr_down, bool count, bool bond,
+                                             Obs& o)
+{
+    Vec<D> out;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        uint32_t nb[2 * DIM];
+        nb[0] = same.w[d];
+        nb[1] = side[d];
+        nb[2] = up.w[d];
+        nb[3] = down.w[d];
+        if constexpr (DIM == 3) {
+            nb[4] = zm->w[d];
+            nb[5] = zp->w[d];
+        }
+        const uint32_t g = g0 + d;
+        if constexpr (KIND == KIND_ISING_HALF) {
+            const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
+            out.w[d] = half_word<DIM>(own.w[d], nb, w, reinterpret_cast<const uint8_t*>(lut.e));
+            if (count) half_obs<DIM>(own.w[d], out.w[d], nb, bond, o);
+        } else if constexpr (KIND == KIND_ISING_ONE) {
+            const Words4 wa = philox4x32_10(2 * g, colour, t, 0u, ks);
+            const Words4 wb = philox4x32_10(2 * g + 1, colour, t, 0u, ks);
+            out.w[d] = one_word<DIM>(own.w[d], nb, wa, wb, lut, count, bond, o);
+        } else {
+            const uint32_t east = p ? nb[1] : nb[0];
+            const uint32_t west = p ? nb[0] : nb[1];
+            out.w[d] = ne_word(own.w[d], nb[2], east, g, colour, t, ks, thr_up, thr_down);
+            if (count) ne_obs(own.w[d], out.w[d], nb[2], nb[3], east, west, bond, o);
+        }
+    }
+    return out;
+}
+
+// Final per-lane values in record units.
+template <int KIND, int DIM>
+__device__ __forceinline__ void finish_obs(Obs& o, int32_t words_all, int32_t words_c1)
+{
+    if constexpr (KIND == KIND_ISING_HALF) {
+        constexpr int z = 2 * DIM;
+        o.acc /= 7;
+        o.mag = 4 * words_all - 2 * o.mag;
+        o.bond = 4 * z * words_c1 - o.bond / 2;
+    }
+}
+
+__device__ __forceinline__ Lanes lanes_of(const RowGeom& rg, bool xw)
+{
+    Lanes ln;
+    ln.lane = threadIdx.x & 63u;
+    ln.wave = threadIdx.x >> 6;
+    if (xw) {
+        ln.pos = threadIdx.x;
+        ln.src_l = ln.src_r = 0;
+    } else {
+        const uint32_t slot = ln.lane / rg.R;
+        ln.pos = ln.lane - slot * rg.R;
+        const uint32_t base = slot * rg.R;
+        ln.src_l = base + (ln.pos == 0 ? rg.R - 1 : ln.pos - 1);
+        ln.src_r = base + (ln.pos + 1 == rg.R ? 0 : ln.pos + 1);
+    }
+    return ln;
+}
+
+// Item (strip, plane) of this lane, or >= nitems if idle.
+__device__ __forceinline__ uint32_t row_item(const RowGeom& rg, bool xw, const Lanes& ln)
+{
+    const uint32_t b = remap_block();
+    if (xw) return b;
+    const uint32_t slot = ln.lane / rg.R;
+    if (slot >= rg.slots) return 0xFFFFFFFFu;
+    return (b * (blockDim.x >> 6) + ln.wave) * rg.slots + slot;
+}
+
+// ---- HALF -----------------------------------------------------------------
+template <int KIND, int DIM, int D, bool XW>
+__global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
+{
+    __shared__ RowLuts lut;
+    __shared__ uint32_t xch[2][16][2];
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down);
+    __syncthreads();
+
+    Obs o = {0, 0, 0, 0};
+    int32_t words_all = 0, words_c1 = 0;
+    const Lanes ln = lanes_of(rg, XW);
+    const uint32_t item = row_item(rg, XW, ln);
+    if (item < rg.nitems) {  // block-uniform when XW
+        const uint32_t strip = item % rg.nstrips;
+        const uint32_t zp = item / rg.nstrips;
+        const uint32_t L = rg.L;
+        const uint32_t c = a.colour;
+        const uint8_t* O = a.col[c ^ 1u];
+        uint8_t* A = a.col[c];
+        const uint64_t rowb = rg.Lh;
+        const uint64_t cb = 4ull * D * ln.pos;
+        const uint64_t plane = (uint64_t)zp * L;
+        const uint64_t planem = (uint64_t)wrapr((int)zp - 1, L) * L;
+        const uint64_t planep = (uint64_t)wrapr((int)zp + 1, L) * L;
+        const uint32_t y0 = strip * rg.H;
+        const uint32_t y1 = min(y0 + rg.H, L);
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        const bool bond = c == 1;
+        const uint32_t nwv = rg.nw;
+
+        Vec<D> Om = ldv<D>(O, (plane + wrapr((int)y0 - 1, L)) * rowb + cb);
+        Vec<D> O0 = ldv<D>(O, (plane + y0) * rowb + cb);
+        Vec<D> Op = ldv<D>(O, (plane + wrapr((int)y0 + 1, L)) * rowb + cb);
+        Vec<D> own = ldv<D>(A, (plane + y0) * rowb + cb);
+        Vec<D> zmv, zpv;
+        if constexpr (DIM == 3) {
+            zmv = ldv<D>(O, (planem + y0) * rowb + cb);
+            zpv = ldv<D>(O, (planep + y0) * rowb + cb);
+        }
+        uint32_t buf = 0;
+        for (uint32_t y = y0; y < y1; ++y) {
+            // prefetch the next row's words
+            const uint32_t yn = y + 1 == L ? 0 : y + 1;
+            const uint32_t ynn = yn + 1 == L ? 0 : yn + 1;
+            const Vec<D> Op_n = ldv<D>(O, (plane + ynn) * rowb + cb);
+            const Vec<D> own_n = ldv<D>(A, (plane + yn) * rowb + cb);
+            Vec<D> zm_n, zp_n;
+            if constexpr (DIM == 3) {
+                zm_n = ldv<D>(O, (planem + yn) * rowb + cb);
+                zp_n = ldv<D>(O, (planep + yn) * rowb + cb);
+            }
+            const uint32_t p = (y + zp + c) & 1u;
+            uint32_t e = 0;
+            if constexpr (XW) {
+                if (ln.lane == 63) xch[buf][ln.wave][1] = O0.w[D - 1];
+                if (ln.lane == 0) xch[buf][ln.wave][0] = O0.w[0];
+                __syncthreads();
+                if (ln.lane == 0) e = xch[buf][ln.wave == 0 ? nwv - 1 : ln.wave - 1][1];
+                if (ln.lane == 63) e = xch[buf][ln.wave + 1 == nwv ? 0 : ln.wave + 1][0];
+                buf ^= 1u;
+            }
+            const uint32_t x = shift_in<XW>(O0.w[D - 1], O0.w[0], p, ln, e);
+            uint32_t side[D];
+            side_words<D>(O0, x, p, side);
+            const uint32_t g0 = (uint32_t)((plane + y) * rg.ncols + (uint64_t)D * ln.pos);
+            const Vec<D> nw = row_update<KIND, DIM, D>(own, O0, side, Om, Op, &zmv, &zpv, p, g0, c, a.t, ks,
+                                                       lut, thr_up, thr_down, true, bond, o);
+            stv<D>(A, (plane + y) * rowb + cb, nw);
+            words_all += D;
+            if (bond) words_c1 += D;
+            Om = O0;
+            O0 = Op;
+            Op = Op_n;
+            own = own_n;
+            if constexpr (DIM == 3) {
+                zmv = zm_n;
+                zpv = zp_n;
+            }
+        }
+    }
+    finish_obs<KIND, DIM>(o, words_all, words_c1);
+    block_accumulate(o.bond, o.mag, o.acc, o.unfl, a.acc);
+}
+
+// ---- FUSED (2D) -------------------------------------------------------------
+template <int KIND, int D, bool XW>
+struct FusedState {
+    Vec<D> c1a, c1b, c1d;  // old colour-1 rows i-1, i, i+1
+    Vec<D> c1n;            // prefetched old colour-1 row i+2
+    Vec<D> own0, own0n;    // old colour-0 row i, prefetched row i+1
+    Vec<D> n0a, n0b;       // new colour-0 rows i-2, i-1
+};
+
+template <int KIND, int D, bool XW, bool DO_C1, bool STORE0>
+__device__ __forceinline__ void fused_step(int i, FusedState<KIND, D, XW>& st, const RowGeom& rg,
+                                           const Lanes& ln, const uint8_t* S0, const uint8_t* S1,
+                                           uint8_t* D0, uint8_t* D1, uint32_t (&xch)[2][16][4],
+                                           uint32_t& buf, const SweepArgs& a, const PhiloxKey& ks,
+                                           const RowLuts& lut, uint64_t thr_up, uint64_t thr_down,
+                                           Obs& o, int32_t& words_all, int32_t& words_c1)
+{
+    const uint32_t L = rg.L;
+    const uint64_t rowb = rg.Lh;
+    const uint64_t cb = 4ull * D * ln.pos;
+    const uint32_t yi = wrapr(i, L);
+    // prefetch for step i+1: old colour-1 row i+3, old colour-0 row i+1
+    st.c1n = ldv<D>(S1, (uint64_t)wrapr(i + 2, L) * rowb + cb);
+    st.own0n = ldv<D>(S0, (uint64_t)wrapr(i + 1, L) * rowb + cb);
+    const uint32_t p = yi & 1u;  // colour 0 at row i and colour 1 at row i-1 share p
+    uint32_t e0 = 0, e1 = 0;
+    if constexpr (XW) {
+        const uint32_t nwv = rg.nw;
+        if (ln.lane == 63) {
+            xch[buf][ln.wave][1] = st.c1b.w[D - 1];
+            xch[buf][ln.wave][3] = st.n0b.w[D - 1];
+        }
+        if (ln.lane == 0) {
+            xch[buf][ln.wave][0] = st.c1b.w[0];
+            xch[buf][ln.wave][2] = st.n0b.w[0];
+        }
+        __syncthreads();
+        const uint32_t wl = ln.wave == 0 ? nwv - 1 : ln.wave - 1;
+        const uint32_t wr = ln.wave + 1 == nwv ? 0 : ln.wave + 1;
+        if (ln.lane == 0) {
+            e0 = xch[buf][wl][1];
+            e1 = xch[buf][wl][3];
+        }
+        if (ln.lane == 63) {
+            e0 = xch[buf][wr][0];
+            e1 = xch[buf][wr][2];
+        }
+        buf ^= 1u;
+    }
+    // colour 0, row i: neighbours old colour-1 rows i-1, i, i+1
+    const uint32_t x0 = shift_in<XW>(st.c1b.w[D - 1], st.c1b.w[0], p, ln, e0);
+    uint32_t side0[D];
+    side_words<D>(st.c1b, x0, p, side0);
+    const uint32_t g0 = yi * rg.ncols + D * ln.pos;
+    const Vec<D> new0 = row_update<KIND, 2, D>(st.own0, st.c1b, side0, st.c1a, st.c1d, nullptr, nullptr, p,
+                                               g0, 0u, a.t, ks, lut, thr_up, thr_down, STORE0, false, o);
+    if (STORE0) {
+        stv<D>(D0, (uint64_t)yi * rowb + cb, new0);
+        words_all += D;
+    }
+    if (DO_C1) {
+        // colour 1, row i-1: neighbours new colour-0 rows i-2, i-1, i
+        const uint32_t ym = wrapr(i - 1, L);
+        const uint32_t x1 = shift_in<XW>(st.n0b.w[D - 1], st.n0b.w[0], p, ln, e1);
+        uint32_t side1[D];
+        side_words<D>(st.n0b, x1, p, side1);
+        const uint32_t g1 = ym * rg.ncols + D * ln.pos;
+        const Vec<D> new1 = row_update<KIND, 2, D>(st.c1a, st.n0b, side1, st.n0a, new0, nullptr, nullptr, p,
+                                                   g1, 1u, a.t, ks, lut, thr_up, thr_down, true, true, o);
+        stv<D>(D1, (uint64_t)ym * rowb + cb, new1);
+        words_all += D;
+        words_c1 += D;
+    }
+    st.c1a = st.c1b;
+    st.c1b = st.c1d;
+    st.c1d = st.c1n;
+    st.own0 = st.own0n;
+    st.n0a = st.n0b;
+    st.n0b = new0;
+}
+
+template <int KIND, int D, bool XW>
+__global__ void __launch_bounds__(1024) k_row_fused(SweepArgs a, RowGeom rg, const uint8_t* S0,
+                                                    const uint8_t* S1, uint8_t* D0, uint8_t* D1)
+{
+    __shared__ RowLuts lut;
+    __shared__ uint32_t xch[2][16][4];
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down);
+    __syncthreads();
+
+    Obs o = {0, 0, 0, 0};
+    int32_t words_all = 0, words_c1 = 0;
+    const Lanes ln = lanes_of(rg, XW);
+    const uint32_t item = row_item(rg, XW, ln);
+    if (item < rg.nitems) {
+        const uint32_t L = rg.L;
+        const uint64_t rowb = rg.Lh;
+        const uint64_t cb = 4ull * D * ln.pos;
+        const int y0 = (int)(item * rg.H);
+        const int y1 = min(y0 + (int)rg.H, (int)L);
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        FusedState<KIND, D, XW> st;
+        st.c1a = ldv<D>(S1, (uint64_t)wrapr(y0 - 2, L) * rowb + cb);
+        st.c1b = ldv<D>(S1, (uint64_t)wrapr(y0 - 1, L) * rowb + cb);
+        st.c1d = ldv<D>(S1, (uint64_t)wrapr(y0, L) * rowb + cb);
+        st.own0 = ldv<D>(S0, (uint64_t)wrapr(y0 - 1, L) * rowb + cb);
+#pragma unroll
+        for (int d = 0; d < D; ++d) st.n0a.w[d] = st.n0b.w[d] = 0u;
+        uint32_t buf = 0;
+        fused_step<KIND, D, XW, false, false>(y0 - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                              thr_up, thr_down, o, words_all, words_c1);
+        fused_step<KIND, D, XW, false, true>(y0, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut, thr_up,
+                                             thr_down, o, words_all, words_c1);
+        for (int i = y0 + 1; i < y1; ++i)
+            fused_step<KIND, D, XW, true, true>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                thr_up, thr_down, o, words_all, words_c1);
+        fused_step<KIND, D, XW, true, false>(y1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut, thr_up,
+                                             thr_down, o, words_all, words_c1);
+    }
+    finish_obs<KIND, 2>(o, words_all, words_c1);
+    block_accumulate(o.bond, o.mag, o.acc, o.unfl, a.acc);
+}
+
+// ---- host side ----------------------------------------------------------------
+bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg)
+{
+    rg = RowGeom{};
+    rg.L = g.L;
+    rg.Lh = g.Lh;
+    rg.ncols = g.Lh / 4;
+    if (D != 1 && D != 2 && D != 4) return false;
+    if (rg.ncols % (uint32_t)D) return false;
+    rg.D = (uint32_t)D;
+    rg.R = rg.ncols / rg.D;
+    if (rg.R <= 64) {
+        rg.slots = 64 / rg.R;
+        rg.nw = 1;
+        rg.block = 256;
+    } else {
+        if (rg.R % 64 || rg.R > 1024) return false;
+        rg.slots = 1;
+        rg.nw = rg.R / 64;
+        rg.block = rg.R;
+    }
+    if (fused && g.dim != 2) return false;
+    rg.nplanes = g.dim == 3 ? g.L : 1;
+    rg.H = (uint32_t)H;
+    rg.nstrips = cdiv(g.L, rg.H);
+    rg.nitems = rg.nstrips * rg.nplanes;
+    return true;
+}
+
+unsigned row_blocks(const RowGeom& rg)
+{
+    if (rg.R > 64) return rg.nitems;
+    return cdiv(rg.nitems, (rg.block / 64) * rg.slots);
+}
+
+template <int KIND, int DIM, int D>
+void launch_half_d(const SweepArgs& a, const RowGeom& rg, hipStream_t s)
+{
+    if (rg.R > 64)
+        hipLaunchKernelGGL((k_row_half<KIND, DIM, D, true>), dim3(row_blocks(rg)), dim3(rg.block), 0, s, a, rg);
+    else
+        hipLaunchKernelGGL((k_row_half<KIND, DIM, D, false>), dim3(row_blocks(rg)), dim3(rg.block), 0, s, a, rg);
+}
+
+template <int KIND, int DIM>
+void launch_half_k(const SweepArgs& a, const RowGeom& rg, hipStream_t s)
+{
+    if (rg.D == 4) launch_half_d<KIND, DIM, 4>(a, rg, s);
+    else if (rg.D == 2) launch_half_d<KIND, DIM, 2>(a, rg, s);
+    else launch_half_d<KIND, DIM, 1>(a, rg, s);
+}
+
+template <int KIND, int D>
+void launch_fused_d(const SweepArgs& a, const RowGeom& rg, const uint8_t* s0, const uint8_t* s1, uint8_t* d0,
+                    uint8_t* d1, hipStream_t s)
+{
+    if (rg.R > 64)
+        hipLaunchKernelGGL((k_row_fused<KIND, D, true>), dim3(row_blocks(rg)), dim3(rg.block), 0, s, a, rg, s0,
+                           s1, d0, d1);
+    else
+        hipLaunchKernelGGL((k_row_fused<KIND, D, false>), dim3(row_blocks(rg)), dim3(rg.block), 0, s, a, rg, s0,
+                           s1, d0, d1);
+}
+
+template <int KIND>
+void launch_fused_k(const SweepArgs& a, const RowGeom& rg, const uint8_t* s0, const uint8_t* s1, uint8_t* d0,
+                    uint8_t* d1, hipStream_t s)
+{
+    if (rg.D == 4) launch_fused_d<KIND, 4>(a, rg, s0, s1, d0, d1, s);
+    else if (rg.D == 2) launch_fused_d<KIND, 2>(a, rg, s0, s1, d0, d1, s);
+    else launch_fused_d<KIND, 1>(a, rg, s0, s1, d0, d1, s);
+}
+
+}  // namespace
+
+bool row_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused, bool lut32_ok)
+{
+    if (kind == KIND_ISING_HALF && !lut32_ok) return false;
+    RowGeom rg;
+    return tile_rows >= 1 && make_row_geom(g, tile_rows, tile_words, fused, rg);
+}
+
+hipError_t launch_row_half(const SweepArgs& a, int kind, int H, int D, hipStream_t s)
+{
+    RowGeom rg;
+    if (!make_row_geom(a.g, H, D, false, rg)) return hipErrorInvalidValue;
+    if (a.g.dim == 2) {
+        if (kind == KIND_ISING_HALF) launch_half_k<KIND_ISING_HALF, 2>(a, rg, s);
+        else if (kind == KIND_ISING_ONE) launch_half_k<KIND_ISING_ONE, 2>(a, rg, s);
+        else launch_half_k<KIND_NE, 2>(a, rg, s);
+    } else {
+        if (kind == KIND_ISING_HALF) launch_half_k<KIND_ISING_HALF, 3>(a, rg, s);
+        else launch_half_k<KIND_ISING_ONE, 3>(a, rg, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row_fused(const SweepArgs& a, int kind, int H, int D, const uint8_t* src0,
+                            const uint8_t* src1, uint8_t* dst0, uint8_t* dst1, hipStream_t s)
+{
+    RowGeom rg;
+    if (!make_row_geom(a.g, H, D, true, rg)) return hipErrorInvalidValue;
+    if (kind == KIND_ISING_HALF) launch_fused_k<KIND_ISING_HALF>(a, rg, src0, src1, dst0, dst1, s);
+    else if (kind == KIND_ISING_ONE) launch_fused_k<KIND_ISING_ONE>(a, rg, src0, src1, dst0, dst1, s);
+    else launch_fused_k<KIND_NE>(a, rg, src0, src1, dst0, dst1, s);
+    return hipGetLastError();
+}
+
+}  // namespace spinlat

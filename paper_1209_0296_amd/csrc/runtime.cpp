@@ -192,27 +192,81 @@ unsigned long long* slot_ptr(const sl_lattice* h, uint64_t idx)
     return reinterpret_cast<unsigned long long*>(h->base + h->lay.off_acc) + idx * kSlotWords;
 }
 
+bool lut32_ok(const sl_lattice* h)
+{
+    for (size_t i = 0; i < h->table_n; ++i)
+        if (h->table[i] == 0) return false;
+    return true;
+}
+
 // Default schedule for a shape: 2D lattices take one fused launch per sweep,
 // 3D lattices two in-place half-sweeps (a fused 3D sweep would recompute a
-// halo in two directions).
+// halo in two directions).  Strip height H and words per lane D are the
+// fastest measured on MI355X for 2D L = 8192 (spin-1/2: H 8, D 4), NE
+// L = 4096 (H 4, D 2) and 3D L = 256 (H 4, D 4); other widths are tried in
+// order when D does not divide the row, and shapes the whole-row kernels
+// cannot take fall back to the window kernels.
 sl_launch auto_launch(const sl_lattice* h)
 {
+    const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
+                    0u, h->lay.nh};
+    const bool fused = h->params.dim == 2;
+    int H = 8, Ds[3] = {4, 2, 1};
+    if (h->params.dim == 3) {
+        H = 4;
+    } else if (h->kind == KIND_NE) {
+        H = 4;
+        Ds[0] = 2;
+        Ds[1] = 4;
+    } else if (h->kind == KIND_ISING_ONE) {
+        Ds[0] = 2;
+        Ds[1] = 4;
+    }
     sl_launch l{};
-    l.mode = h->params.dim == 2 ? SL_MODE_FUSED : SL_MODE_HALF;
+    for (int D : Ds)
+        if (row_supported(g, h->kind, H, D, fused, lut32_ok(h))) {
+            l.mode = fused ? SL_MODE_FUSED : SL_MODE_HALF;
+            l.tile_rows = H;
+            l.tile_words = D;
+            return l;
+        }
+    l.mode = fused ? SL_MODE_FUSED_WINDOW : SL_MODE_HALF_WINDOW;
     l.tile_rows = 0;
     l.tile_words = 0;
     return l;
 }
 
-sl_status check_launch(const sl_lattice* h, const sl_launch* l)
+sl_status check_launch(const sl_lattice* h, sl_launch* l)
 {
-    if (l->mode == SL_MODE_SIMPLE) return SL_OK;
-    if (l->mode == SL_MODE_HALF || l->mode == SL_MODE_FUSED) {
-        SweepArgs a = args_of(h);
-        if (!tiled_supported(a.g, h->kind, l->tile_rows, l->tile_words, l->mode == SL_MODE_FUSED))
-            return fail(SL_E_UNSUPPORTED, "tile %d rows x %d words not supported for this shape "
-                                          "and mode %d", l->tile_rows, l->tile_words, l->mode);
-        return SL_OK;
+    const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
+                    0u, h->lay.nh};
+    switch (l->mode) {
+        case SL_MODE_SIMPLE:
+            return SL_OK;
+        case SL_MODE_HALF:
+        case SL_MODE_FUSED: {
+            const bool fused = l->mode == SL_MODE_FUSED;
+            if (l->tile_rows == 0) l->tile_rows = 8;
+            if (l->tile_words == 0) {  // first width that fits
+                l->tile_words = 2;
+                for (int D : {2, 4, 1})
+                    if (row_supported(g, h->kind, l->tile_rows, D, fused, lut32_ok(h))) {
+                        l->tile_words = D;
+                        break;
+                    }
+            }
+            if (!row_supported(g, h->kind, l->tile_rows, l->tile_words, fused, lut32_ok(h)))
+                return fail(SL_E_UNSUPPORTED, "mode %d with %d rows x %d words per lane does not fit "
+                            "this lattice", l->mode, l->tile_rows, l->tile_words);
+            return SL_OK;
+        }
+        case SL_MODE_HALF_WINDOW:
+        case SL_MODE_FUSED_WINDOW:
+            if (!tiled_supported(g, h->kind, l->tile_rows, l->tile_words,
+                                 l->mode == SL_MODE_FUSED_WINDOW))
+                return fail(SL_E_UNSUPPORTED, "window mode %d with %d rows x %d words does not fit "
+                            "this lattice", l->mode, l->tile_rows, l->tile_words);
+            return SL_OK;
     }
     return fail(SL_E_INVALID, "unknown launch mode %d", l->mode);
 }
@@ -354,12 +408,17 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
         a.t = (uint32_t)(h->next_t + i);
         a.acc = slot_ptr(h, h->pending + i);
         hipError_t e = hipSuccess;
+        const int H = h->launch.tile_rows, D = h->launch.tile_words;
         switch (h->launch.mode) {
-            case SL_MODE_FUSED: {
+            case SL_MODE_FUSED:
+            case SL_MODE_FUSED_WINDOW: {
                 const int nxt = h->cur ^ 1;
                 uint8_t* d0 = h->base + h->lay.off_col[nxt][0];
                 uint8_t* d1 = h->base + h->lay.off_col[nxt][1];
-                e = launch_fused_sweep(a, h->kind, a.col[0], a.col[1], d0, d1, h->stream);
+                if (h->launch.mode == SL_MODE_FUSED)
+                    e = launch_row_fused(a, h->kind, H, D, a.col[0], a.col[1], d0, d1, h->stream);
+                else
+                    e = launch_fused_sweep(a, h->kind, a.col[0], a.col[1], d0, d1, h->stream);
                 if (e == hipSuccess) {
                     h->cur = nxt;
                     a.col[0] = d0;
@@ -368,9 +427,11 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
                 break;
             }
             case SL_MODE_HALF:
+            case SL_MODE_HALF_WINDOW:
                 for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
                     a.colour = c;
-                    e = launch_tiled_half(a, h->kind, h->stream);
+                    e = h->launch.mode == SL_MODE_HALF ? launch_row_half(a, h->kind, H, D, h->stream)
+                                                       : launch_tiled_half(a, h->kind, h->stream);
                 }
                 break;
             default:

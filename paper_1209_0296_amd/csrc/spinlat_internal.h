@@ -55,7 +55,14 @@ hipError_t launch_fused_sweep(const SweepArgs& a, int kind, const uint8_t* src0,
 hipError_t launch_fold(unsigned long long* acc, int64_t* out, uint64_t n, uint64_t t_first,
                        int ising, hipStream_t s);
 
-// Shape limits of the streaming kernels (checked by the runtime before launch).
+// Shape limits of the window-streaming kernels (checked by the runtime before launch).
 bool tiled_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused);
+
+// Whole-row kernels: tile_rows = strip height H >= 1, tile_words = words per
+// lane D in {1, 2, 4}; spin-1/2 needs every threshold >= 1 (lut32_ok).
+bool row_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused, bool lut32_ok);
+hipError_t launch_row_half(const SweepArgs& a, int kind, int H, int D, hipStream_t s);
+hipError_t launch_row_fused(const SweepArgs& a, int kind, int H, int D, const uint8_t* src0,
+                            const uint8_t* src1, uint8_t* dst0, uint8_t* dst1, hipStream_t s);
 
 }  // namespace spinlat
