@@ -18,6 +18,12 @@
 //
 // Spin-1/2 acceptance uses a 32-bit table of thr-1 (requires every threshold
 // >= 1; the runtime sends other tables to the generic kernels).
+//
+// Neighbour words are "prepared" once per row and reused by the three rows
+// that read them: spin-1/2 keeps bit 2 of each byte (4 per -1 spin), so the
+// sum of prepared neighbours is 4 x (number of -1 neighbours) per byte;
+// spin-1 keeps s+1; NE keeps n.  The row parity p (which side the same-row
+// neighbour sits on) is a template parameter chosen by a uniform branch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -97,26 +103,28 @@ struct Lanes {
     uint32_t lane, wave, pos, src_l, src_r;
 };
 
-template <bool XW>
-__device__ __forceinline__ uint32_t shift_in(uint32_t last, uint32_t first, uint32_t p, const Lanes& ln,
-                                             uint32_t e)
+template <bool XW, int P>
+__device__ __forceinline__ uint32_t shift_in(uint32_t last, uint32_t first, const Lanes& ln, uint32_t e)
 {
     // e: value the wave-edge lane takes (from LDS) when XW
     if constexpr (XW) {
-        if (p == 0) return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)last, 0x138, 0xF, 0xF, false);
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)first, 0x130, 0xF, 0xF, false);
+        if constexpr (P == 0) return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)last, 0x138, 0xF, 0xF, false);
+        else return (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)first, 0x130, 0xF, 0xF, false);
     } else {
-        return (uint32_t)__shfl((int)(p ? first : last), (int)(p ? ln.src_r : ln.src_l), 64);
+        if constexpr (P == 0) return (uint32_t)__shfl((int)last, (int)ln.src_l, 64);
+        else return (uint32_t)__shfl((int)first, (int)ln.src_r, 64);
     }
 }
 
-// Aligned neighbour words of the D words of a lane in the same row.
-template <int D>
-__device__ __forceinline__ void side_words(const Vec<D>& o, uint32_t x, uint32_t p, uint32_t (&s)[D])
+// Aligned neighbour words of the D words of a lane in the same row (P = row
+// parity): P = 0 takes the site to the left (k-1), P = 1 to the right (k+1);
+// x is the adjacent lane's edge word.
+template <int D, int P>
+__device__ __forceinline__ void side_words(const Vec<D>& o, uint32_t x, uint32_t (&s)[D])
 {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        if (p == 0) {
+        if constexpr (P == 0) {
             const uint32_t prev = d > 0 ? o.w[d > 0 ? d - 1 : 0] : x;
             s[d] = __builtin_amdgcn_alignbyte(o.w[d], prev, 3);
         } else {
@@ -139,9 +147,10 @@ __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* tab
     for (int t = threadIdx.x; t < 6 * (2 * z + 1); t += blockDim.x) {
         if (KIND == KIND_ISING_HALF) {
             if (t < 2 * (z + 1)) {
-                const int sneg = t / (z + 1), m = t % (z + 1);
+                // entry nd + sneg*(z+1): nd neighbours at -1, sneg = (s == -1)
+                const int sneg = t / (z + 1), nd = t % (z + 1);
                 const int s = sneg ? -1 : 1;
-                const int nsum = s * (z - 2 * m);
+                const int nsum = z - 2 * nd;
                 const int di = s > 0 ? 0 : 3;
                 // thr >= 1 here: accept iff word <= thr - 1
                 reinterpret_cast<uint32_t*>(lut.e)[t] =
@@ -163,20 +172,41 @@ __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* tab
 }
 
 struct Obs {
-    int32_t bond, mag, acc, unfl;
+    int32_t acc;   // spin-1/2: 7 x accepted moves; others: accepted moves
+    int32_t mag0;  // sum of s (NE: n) over colour-0 words
+    int32_t mag1;  // same over colour-1 words
+    int32_t dd;    // spin-1/2: sum s' * 4 nd; spin-1: sum s' * (nsum + z); NE: bond
+    int32_t unfl;  // NE: sites with the flip flag clear
 };
 
-// ---- one word -----------------------------------------------------------------
-// nb: [same, side, y-1, y+1, (z-1, z+1)] aligned to the word's four sites.
-template <int DIM>
-__device__ __forceinline__ uint32_t half_word(uint32_t own, const uint32_t (&nb)[2 * DIM], const Words4& w,
-                                              const uint8_t* lut_bytes)
+// prepared form of an other-colour word
+template <int KIND>
+__device__ __forceinline__ uint32_t prep(uint32_t w)
 {
-    constexpr int z = 2 * DIM;
-    uint32_t mis = 0;
+    if constexpr (KIND == KIND_ISING_HALF) return w & M4;
+    else if constexpr (KIND == KIND_ISING_ONE) return (w ^ 0x80808080u) + 0x80808081u;  // s+1, no carries
+    else return w & 0x01010101u;
+}
+
+template <int KIND, int D>
+__device__ __forceinline__ Vec<D> prepv(const Vec<D>& v)
+{
+    Vec<D> o;
 #pragma unroll
-    for (int j = 0; j < z; ++j) mis += (nb[j] ^ own) & M4;  // 4 per anti-aligned neighbour
-    const uint32_t idx4 = mis + (own & M4) * (uint32_t)(z + 1);
+    for (int d = 0; d < D; ++d) o.w[d] = prep<KIND>(v.w[d]);
+    return o;
+}
+
+__device__ __forceinline__ int dot4(uint32_t a, uint32_t b, int c)
+{
+    return __builtin_amdgcn_sdot4((int)a, (int)b, c, false);
+}
+
+// spin-1/2: nd4 = 4 x (number of -1 neighbours) per byte
+__device__ __forceinline__ uint32_t half_word(uint32_t own, uint32_t nd4, const Words4& w,
+                                              const uint8_t* lut_bytes, int z)
+{
+    const uint32_t idx4 = nd4 + (own & M4) * (uint32_t)(z + 1);
     uint32_t flip = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -187,33 +217,13 @@ __device__ __forceinline__ uint32_t half_word(uint32_t own, const uint32_t (&nb)
     return own ^ flip;
 }
 
+// spin-1: S = per-byte nsum + z
 template <int DIM>
-__device__ __forceinline__ void half_obs(uint32_t own, uint32_t nw, const uint32_t (&nb)[2 * DIM], bool bond,
-                                         Obs& o)
+__device__ __forceinline__ uint32_t one_word(uint32_t own, uint32_t S, const Words4& wa, const Words4& wb,
+                                             const RowLuts& lut, int& nacc)
 {
     constexpr int z = 2 * DIM;
-    o.acc += __builtin_popcount(own ^ nw);         // 7 per flip
-    o.mag += __builtin_popcount(nw & 0x02020202u);  // number of -1 spins
-    if (bond) {
-        uint32_t mis = 0;
-#pragma unroll
-        for (int j = 0; j < z; ++j) mis += (nb[j] ^ nw) & M4;
-        o.bond += (int)__builtin_amdgcn_sad_u8(mis, 0u, 0u);  // 4 * anti-aligned bonds
-    }
-}
-
-__device__ __forceinline__ uint32_t bias1(uint32_t v) { return (v ^ 0x80808080u) + 0x80808081u; }
-
-template <int DIM>
-__device__ __forceinline__ uint32_t one_word(uint32_t own, const uint32_t (&nb)[2 * DIM], const Words4& wa,
-                                             const Words4& wb, const RowLuts& lut, bool count, bool bond,
-                                             Obs& o)
-{
-    constexpr int z = 2 * DIM;
-    uint32_t S = 0;
-#pragma unroll
-    for (int j = 0; j < z; ++j) S += bias1(nb[j]);
-    const uint32_t ob = bias1(own);
+    const uint32_t ob = prep<KIND_ISING_ONE>(own);
     uint32_t out = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -223,13 +233,10 @@ __device__ __forceinline__ uint32_t one_word(uint32_t own, const uint32_t (&nb)[
         const uint32_t s1 = (ob >> (8 * b)) & 0xFFu;
         const uint32_t nz = (S >> (8 * b)) & 0xFFu;
         const uint64_t ent = lut.e[(s1 * 2 + (up >> 31)) * (2 * z + 1) + nz];
-        const uint32_t n1 = ((uint64_t)ua < (ent & 0x1FFFFFFFFull)) ? (uint32_t)(ent >> 40) : s1;
+        const bool acc = (uint64_t)ua < (ent & 0x1FFFFFFFFull);
+        const uint32_t n1 = acc ? (uint32_t)(ent >> 40) : s1;
+        nacc += acc ? 1 : 0;
         out |= ((n1 - 1u) & 0xFFu) << (8 * b);
-        if (count) {
-            o.acc += n1 != s1;
-            o.mag += (int)n1 - 1;
-            if (bond) o.bond += ((int)n1 - 1) * ((int)nz - z);
-        }
     }
     return out;
 }
@@ -238,8 +245,9 @@ __device__ __forceinline__ uint32_t ne_word(uint32_t own, uint32_t north, uint32
                                             uint32_t colour, uint32_t t, const PhiloxKey& ks,
                                             uint64_t thr_up, uint64_t thr_down)
 {
+    // north, east: prepared (n bits)
     const uint32_t n = own & 0x01010101u;
-    const uint32_t allowed = north & east & 0x01010101u;
+    const uint32_t allowed = north & east;
     const uint32_t up = allowed & ~n;
     const uint32_t down = allowed & n;
     const bool up_rand = thr_up < (1ull << 32);
@@ -258,68 +266,89 @@ __device__ __forceinline__ uint32_t ne_word(uint32_t own, uint32_t north, uint32
     return (own ^ f) | (f << 1);
 }
 
-__device__ __forceinline__ void ne_obs(uint32_t own, uint32_t nw, uint32_t north, uint32_t south,
-                                       uint32_t east, uint32_t west, bool bond, Obs& o)
-{
-    o.acc += __builtin_popcount((own ^ nw) & 0x01010101u);
-    o.mag += __builtin_popcount(nw & 0x01010101u);
-    o.unfl += 4 - __builtin_popcount(nw & 0x02020202u);
-    if (bond) {
-        const uint32_t m = 0x01010101u;
-        const uint32_t s = (north & m) + (south & m) + (east & m) + (west & m);
-        o.bond += (int)__builtin_amdgcn_sad_u8(s & ((nw & m) * 0xFFu), 0u, 0u);
-    }
-}
-
-// Update the D words of one lane in one row.  g0 = Philox group of word 0.
-template <int KIND, int DIM, int D>
+// Update the D words of one lane in one row.  Neighbour words are prepared;
+// `side` are the prepared same-row neighbours aligned to the words.
+template <int KIND, int DIM, int D, int P>
 __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& same, const uint32_t (&side)[D],
                                              const Vec<D>& up, const Vec<D>& down, const Vec<D>* zm,
-                                             const Vec<D>* zp, uint32_t p, uint32_t g0, uint32_t colour,
-                                             uint32_t t, const PhiloxKey& ks, const RowLuts& lut,
-                                             uint64_t thr_up, uint64_t thr_down, bool count, bool bond,
-                                             Obs& o)
+                                             const Vec<D>* zp, uint32_t g0, uint32_t colour, uint32_t t,
+                                             const PhiloxKey& ks, const RowLuts& lut, uint64_t thr_up,
+                                             uint64_t thr_down, bool count, Obs& o)
 {
+    constexpr int z = 2 * DIM;
     Vec<D> out;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        uint32_t nb[2 * DIM];
-        nb[0] = same.w[d];
-        nb[1] = side[d];
-        nb[2] = up.w[d];
-        nb[3] = down.w[d];
-        if constexpr (DIM == 3) {
-            nb[4] = zm->w[d];
-            nb[5] = zp->w[d];
-        }
         const uint32_t g = g0 + d;
-        if constexpr (KIND == KIND_ISING_HALF) {
-            const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
-            out.w[d] = half_word<DIM>(own.w[d], nb, w, reinterpret_cast<const uint8_t*>(lut.e));
-            if (count) half_obs<DIM>(own.w[d], out.w[d], nb, bond, o);
-        } else if constexpr (KIND == KIND_ISING_ONE) {
-            const Words4 wa = philox4x32_10(2 * g, colour, t, 0u, ks);
-            const Words4 wb = philox4x32_10(2 * g + 1, colour, t, 0u, ks);
-            out.w[d] = one_word<DIM>(own.w[d], nb, wa, wb, lut, count, bond, o);
+        if constexpr (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE) {
+            uint32_t S = same.w[d] + side[d] + up.w[d] + down.w[d];
+            if constexpr (DIM == 3) S += zm->w[d] + zp->w[d];
+            if constexpr (KIND == KIND_ISING_HALF) {
+                const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
+                out.w[d] = half_word(own.w[d], S, w, reinterpret_cast<const uint8_t*>(lut.e), z);
+                if (count) {
+                    o.acc += __builtin_popcount(own.w[d] ^ out.w[d]);
+                    if (colour == 0) {
+                        o.mag0 = dot4(out.w[d], 0x01010101u, o.mag0);
+                    } else {
+                        o.mag1 = dot4(out.w[d], 0x01010101u, o.mag1);
+                        o.dd = dot4(out.w[d], S, o.dd);
+                    }
+                }
+            } else {
+                const Words4 wa = philox4x32_10(2 * g, colour, t, 0u, ks);
+                const Words4 wb = philox4x32_10(2 * g + 1, colour, t, 0u, ks);
+                int nacc = 0;
+                out.w[d] = one_word<DIM>(own.w[d], S, wa, wb, lut, nacc);
+                if (count) {
+                    o.acc += nacc;
+                    if (colour == 0) {
+                        o.mag0 = dot4(out.w[d], 0x01010101u, o.mag0);
+                    } else {
+                        o.mag1 = dot4(out.w[d], 0x01010101u, o.mag1);
+                        o.dd = dot4(out.w[d], S, o.dd);
+                    }
+                }
+            }
         } else {
-            const uint32_t east = p ? nb[1] : nb[0];
-            const uint32_t west = p ? nb[0] : nb[1];
-            out.w[d] = ne_word(own.w[d], nb[2], east, g, colour, t, ks, thr_up, thr_down);
-            if (count) ne_obs(own.w[d], out.w[d], nb[2], nb[3], east, west, bond, o);
+            // north = row y-1; east = site x+1 (side word when p = 1)
+            const uint32_t east = P ? side[d] : same.w[d];
+            const uint32_t west = P ? same.w[d] : side[d];
+            out.w[d] = ne_word(own.w[d], up.w[d], east, g, colour, t, ks, thr_up, thr_down);
+            if (count) {
+                const uint32_t n = out.w[d] & 0x01010101u;
+                o.acc += __builtin_popcount((own.w[d] ^ out.w[d]) & 0x01010101u);
+                o.mag0 += __builtin_popcount(n);
+                o.unfl += 4 - __builtin_popcount(out.w[d] & 0x02020202u);
+                if (colour == 1) o.dd = dot4(n, up.w[d] + down.w[d] + east + west, o.dd);
+            }
         }
     }
     return out;
 }
 
-// Final per-lane values in record units.
+// Record units per lane: {bond_sum, mag, accepted, unflipped}.
 template <int KIND, int DIM>
-__device__ __forceinline__ void finish_obs(Obs& o, int32_t words_all, int32_t words_c1)
+__device__ __forceinline__ void finish_obs(const Obs& o, int32_t& bond, int32_t& mag, int32_t& acc,
+                                           int32_t& unfl)
 {
+    constexpr int z = 2 * DIM;
     if constexpr (KIND == KIND_ISING_HALF) {
-        constexpr int z = 2 * DIM;
-        o.acc /= 7;
-        o.mag = 4 * words_all - 2 * o.mag;
-        o.bond = 4 * z * words_c1 - o.bond / 2;
+        // sum_b s'_b nsum_b = z sum s' - 2 sum s' nd, and dd = sum s' * 4 nd
+        bond = z * o.mag1 - o.dd / 2;
+        mag = o.mag0 + o.mag1;
+        acc = o.acc / 7;
+        unfl = 0;
+    } else if constexpr (KIND == KIND_ISING_ONE) {
+        bond = o.dd - z * o.mag1;  // dd = sum s' (nsum + z)
+        mag = o.mag0 + o.mag1;
+        acc = o.acc;
+        unfl = 0;
+    } else {
+        bond = o.dd;
+        mag = o.mag0;
+        acc = o.acc;
+        unfl = o.unfl;
     }
 }
 
@@ -352,6 +381,64 @@ __device__ __forceinline__ uint32_t row_item(const RowGeom& rg, bool xw, const L
 }
 
 // ---- HALF -----------------------------------------------------------------
+template <int KIND, int DIM, int D>
+struct HalfState {
+    Vec<D> Om, O0, Op;    // prepared other-colour rows y-1, y, y+1
+    Vec<D> own;           // own words of row y
+    Vec<D> Opn, ownn;     // prefetched: other row y+2 (raw), own row y+1
+    Vec<D> zm, zp;        // prepared planes z-1, z+1 at row y (3D)
+    Vec<D> zmn, zpn;      // prefetched (raw)
+};
+
+template <int KIND, int DIM, int D, bool XW, int P>
+__device__ __forceinline__ void half_step(uint32_t y, HalfState<KIND, DIM, D>& st, const RowGeom& rg,
+                                          const Lanes& ln, const uint8_t* O, uint8_t* A, uint64_t plane,
+                                          uint64_t planem, uint64_t planep, uint32_t (&xch)[2][16][2],
+                                          uint32_t& buf, const SweepArgs& a, const PhiloxKey& ks,
+                                          const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o)
+{
+    const uint32_t L = rg.L;
+    const uint64_t rowb = rg.Lh;
+    const uint64_t cb = 4ull * D * ln.pos;
+    const uint32_t yn = y + 1 == L ? 0 : y + 1;
+    const uint32_t ynn = yn + 1 == L ? 0 : yn + 1;
+    st.Opn = ldv<D>(O, (plane + ynn) * rowb + cb);
+    st.ownn = ldv<D>(A, (plane + yn) * rowb + cb);
+    if constexpr (DIM == 3) {
+        st.zmn = ldv<D>(O, (planem + yn) * rowb + cb);
+        st.zpn = ldv<D>(O, (planep + yn) * rowb + cb);
+    }
+    uint32_t e = 0;
+    if constexpr (XW) {
+        const uint32_t nwv = rg.nw;
+        if (ln.lane == 63) xch[buf][ln.wave][1] = st.O0.w[D - 1];
+        if (ln.lane == 0) xch[buf][ln.wave][0] = st.O0.w[0];
+        __syncthreads();
+        if constexpr (P == 0) {
+            if (ln.lane == 0) e = xch[buf][ln.wave == 0 ? nwv - 1 : ln.wave - 1][1];
+        } else {
+            if (ln.lane == 63) e = xch[buf][ln.wave + 1 == nwv ? 0 : ln.wave + 1][0];
+        }
+        buf ^= 1u;
+    }
+    const uint32_t x = shift_in<XW, P>(st.O0.w[D - 1], st.O0.w[0], ln, e);
+    uint32_t side[D];
+    side_words<D, P>(st.O0, x, side);
+    const uint32_t c = a.colour;
+    const uint32_t g0 = (uint32_t)((plane + y) * rg.ncols + (uint64_t)D * ln.pos);
+    const Vec<D> nw = row_update<KIND, DIM, D, P>(st.own, st.O0, side, st.Om, st.Op, &st.zm, &st.zp, g0, c,
+                                                  a.t, ks, lut, thr_up, thr_down, true, o);
+    stv<D>(A, (plane + y) * rowb + cb, nw);
+    st.Om = st.O0;
+    st.O0 = st.Op;
+    st.Op = prepv<KIND, D>(st.Opn);
+    st.own = st.ownn;
+    if constexpr (DIM == 3) {
+        st.zm = prepv<KIND, D>(st.zmn);
+        st.zp = prepv<KIND, D>(st.zpn);
+    }
+}
+
 template <int KIND, int DIM, int D, bool XW>
 __global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
 {
@@ -361,8 +448,7 @@ __global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
     build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down);
     __syncthreads();
 
-    Obs o = {0, 0, 0, 0};
-    int32_t words_all = 0, words_c1 = 0;
+    Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, XW);
     const uint32_t item = row_item(rg, XW, ln);
     if (item < rg.nitems) {  // block-uniform when XW
@@ -380,142 +466,131 @@ __global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
         const uint32_t y0 = strip * rg.H;
         const uint32_t y1 = min(y0 + rg.H, L);
         const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-        const bool bond = c == 1;
-        const uint32_t nwv = rg.nw;
 
-        Vec<D> Om = ldv<D>(O, (plane + wrapr((int)y0 - 1, L)) * rowb + cb);
-        Vec<D> O0 = ldv<D>(O, (plane + y0) * rowb + cb);
-        Vec<D> Op = ldv<D>(O, (plane + wrapr((int)y0 + 1, L)) * rowb + cb);
-        Vec<D> own = ldv<D>(A, (plane + y0) * rowb + cb);
-        Vec<D> zmv, zpv;
+        HalfState<KIND, DIM, D> st;
+        st.Om = prepv<KIND, D>(ldv<D>(O, (plane + wrapr((int)y0 - 1, L)) * rowb + cb));
+        st.O0 = prepv<KIND, D>(ldv<D>(O, (plane + y0) * rowb + cb));
+        st.Op = prepv<KIND, D>(ldv<D>(O, (plane + wrapr((int)y0 + 1, L)) * rowb + cb));
+        st.own = ldv<D>(A, (plane + y0) * rowb + cb);
         if constexpr (DIM == 3) {
-            zmv = ldv<D>(O, (planem + y0) * rowb + cb);
-            zpv = ldv<D>(O, (planep + y0) * rowb + cb);
+            st.zm = prepv<KIND, D>(ldv<D>(O, (planem + y0) * rowb + cb));
+            st.zp = prepv<KIND, D>(ldv<D>(O, (planep + y0) * rowb + cb));
         }
         uint32_t buf = 0;
         for (uint32_t y = y0; y < y1; ++y) {
-            // prefetch the next row's words
-            const uint32_t yn = y + 1 == L ? 0 : y + 1;
-            const uint32_t ynn = yn + 1 == L ? 0 : yn + 1;
-            const Vec<D> Op_n = ldv<D>(O, (plane + ynn) * rowb + cb);
-            const Vec<D> own_n = ldv<D>(A, (plane + yn) * rowb + cb);
-            Vec<D> zm_n, zp_n;
-            if constexpr (DIM == 3) {
-                zm_n = ldv<D>(O, (planem + yn) * rowb + cb);
-                zp_n = ldv<D>(O, (planep + yn) * rowb + cb);
-            }
-            const uint32_t p = (y + zp + c) & 1u;
-            uint32_t e = 0;
-            if constexpr (XW) {
-                if (ln.lane == 63) xch[buf][ln.wave][1] = O0.w[D - 1];
-                if (ln.lane == 0) xch[buf][ln.wave][0] = O0.w[0];
-                __syncthreads();
-                if (ln.lane == 0) e = xch[buf][ln.wave == 0 ? nwv - 1 : ln.wave - 1][1];
-                if (ln.lane == 63) e = xch[buf][ln.wave + 1 == nwv ? 0 : ln.wave + 1][0];
-                buf ^= 1u;
-            }
-            const uint32_t x = shift_in<XW>(O0.w[D - 1], O0.w[0], p, ln, e);
-            uint32_t side[D];
-            side_words<D>(O0, x, p, side);
-            const uint32_t g0 = (uint32_t)((plane + y) * rg.ncols + (uint64_t)D * ln.pos);
-            const Vec<D> nw = row_update<KIND, DIM, D>(own, O0, side, Om, Op, &zmv, &zpv, p, g0, c, a.t, ks,
-                                                       lut, thr_up, thr_down, true, bond, o);
-            stv<D>(A, (plane + y) * rowb + cb, nw);
-            words_all += D;
-            if (bond) words_c1 += D;
-            Om = O0;
-            O0 = Op;
-            Op = Op_n;
-            own = own_n;
-            if constexpr (DIM == 3) {
-                zmv = zm_n;
-                zpv = zp_n;
-            }
+            if (((y + zp + c) & 1u) == 0)
+                half_step<KIND, DIM, D, XW, 0>(y, st, rg, ln, O, A, plane, planem, planep, xch, buf, a, ks,
+                                               lut, thr_up, thr_down, o);
+            else
+                half_step<KIND, DIM, D, XW, 1>(y, st, rg, ln, O, A, plane, planem, planep, xch, buf, a, ks,
+                                               lut, thr_up, thr_down, o);
         }
     }
-    finish_obs<KIND, DIM>(o, words_all, words_c1);
-    block_accumulate(o.bond, o.mag, o.acc, o.unfl, a.acc);
+    int32_t bond, mag, acc, unfl;
+    finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
+    block_accumulate(bond, mag, acc, unfl, a.acc);
 }
 
 // ---- FUSED (2D) -------------------------------------------------------------
-template <int KIND, int D, bool XW>
+template <int KIND, int D>
 struct FusedState {
-    Vec<D> c1a, c1b, c1d;  // old colour-1 rows i-1, i, i+1
-    Vec<D> c1n;            // prefetched old colour-1 row i+2
-    Vec<D> own0, own0n;    // old colour-0 row i, prefetched row i+1
-    Vec<D> n0a, n0b;       // new colour-0 rows i-2, i-1
+    Vec<D> c1a, c1b;          // old colour-1 rows i-1, i (raw: c1a is updated at i-1)
+    Vec<D> q1a, q1b, q1d;     // the same rows i-1, i, i+1 prepared
+    Vec<D> c1d, c1n;          // raw row i+1, prefetched raw row i+2
+    Vec<D> own0, own0n;       // old colour-0 row i, prefetched row i+1
+    Vec<D> q0a, q0b;          // new colour-0 rows i-2, i-1 prepared
 };
 
-template <int KIND, int D, bool XW, bool DO_C1, bool STORE0>
-__device__ __forceinline__ void fused_step(int i, FusedState<KIND, D, XW>& st, const RowGeom& rg,
-                                           const Lanes& ln, const uint8_t* S0, const uint8_t* S1,
-                                           uint8_t* D0, uint8_t* D1, uint32_t (&xch)[2][16][4],
-                                           uint32_t& buf, const SweepArgs& a, const PhiloxKey& ks,
-                                           const RowLuts& lut, uint64_t thr_up, uint64_t thr_down,
-                                           Obs& o, int32_t& words_all, int32_t& words_c1)
+template <int KIND, int D, bool XW, int P, bool DO_C1, bool STORE0, bool PREF>
+__device__ __forceinline__ void fused_step(int i, FusedState<KIND, D>& st, const RowGeom& rg, const Lanes& ln,
+                                           const uint8_t* S0, const uint8_t* S1, uint8_t* D0, uint8_t* D1,
+                                           uint32_t (&xch)[2][16][4], uint32_t& buf, const SweepArgs& a,
+                                           const PhiloxKey& ks, const RowLuts& lut, uint64_t thr_up,
+                                           uint64_t thr_down, Obs& o)
 {
     const uint32_t L = rg.L;
     const uint64_t rowb = rg.Lh;
     const uint64_t cb = 4ull * D * ln.pos;
     const uint32_t yi = wrapr(i, L);
-    // prefetch for step i+1: old colour-1 row i+3, old colour-0 row i+1
-    st.c1n = ldv<D>(S1, (uint64_t)wrapr(i + 2, L) * rowb + cb);
-    st.own0n = ldv<D>(S0, (uint64_t)wrapr(i + 1, L) * rowb + cb);
-    const uint32_t p = yi & 1u;  // colour 0 at row i and colour 1 at row i-1 share p
+    if constexpr (PREF) {
+        // for step i+1: old colour-1 row i+2, old colour-0 row i+1
+        st.c1n = ldv<D>(S1, (uint64_t)wrapr(i + 2, L) * rowb + cb);
+        st.own0n = ldv<D>(S0, (uint64_t)wrapr(i + 1, L) * rowb + cb);
+    }
     uint32_t e0 = 0, e1 = 0;
     if constexpr (XW) {
         const uint32_t nwv = rg.nw;
         if (ln.lane == 63) {
-            xch[buf][ln.wave][1] = st.c1b.w[D - 1];
-            xch[buf][ln.wave][3] = st.n0b.w[D - 1];
+            xch[buf][ln.wave][1] = st.q1b.w[D - 1];
+            xch[buf][ln.wave][3] = st.q0b.w[D - 1];
         }
         if (ln.lane == 0) {
-            xch[buf][ln.wave][0] = st.c1b.w[0];
-            xch[buf][ln.wave][2] = st.n0b.w[0];
+            xch[buf][ln.wave][0] = st.q1b.w[0];
+            xch[buf][ln.wave][2] = st.q0b.w[0];
         }
         __syncthreads();
-        const uint32_t wl = ln.wave == 0 ? nwv - 1 : ln.wave - 1;
-        const uint32_t wr = ln.wave + 1 == nwv ? 0 : ln.wave + 1;
-        if (ln.lane == 0) {
-            e0 = xch[buf][wl][1];
-            e1 = xch[buf][wl][3];
-        }
-        if (ln.lane == 63) {
-            e0 = xch[buf][wr][0];
-            e1 = xch[buf][wr][2];
+        if constexpr (P == 0) {
+            if (ln.lane == 0) {
+                const uint32_t wl = ln.wave == 0 ? nwv - 1 : ln.wave - 1;
+                e0 = xch[buf][wl][1];
+                e1 = xch[buf][wl][3];
+            }
+        } else {
+            if (ln.lane == 63) {
+                const uint32_t wr = ln.wave + 1 == nwv ? 0 : ln.wave + 1;
+                e0 = xch[buf][wr][0];
+                e1 = xch[buf][wr][2];
+            }
         }
         buf ^= 1u;
     }
-    // colour 0, row i: neighbours old colour-1 rows i-1, i, i+1
-    const uint32_t x0 = shift_in<XW>(st.c1b.w[D - 1], st.c1b.w[0], p, ln, e0);
+    // colour 0, row i (parity P): neighbours old colour-1 rows i-1, i, i+1
+    const uint32_t x0 = shift_in<XW, P>(st.q1b.w[D - 1], st.q1b.w[0], ln, e0);
     uint32_t side0[D];
-    side_words<D>(st.c1b, x0, p, side0);
+    side_words<D, P>(st.q1b, x0, side0);
     const uint32_t g0 = yi * rg.ncols + D * ln.pos;
-    const Vec<D> new0 = row_update<KIND, 2, D>(st.own0, st.c1b, side0, st.c1a, st.c1d, nullptr, nullptr, p,
-                                               g0, 0u, a.t, ks, lut, thr_up, thr_down, STORE0, false, o);
-    if (STORE0) {
-        stv<D>(D0, (uint64_t)yi * rowb + cb, new0);
-        words_all += D;
-    }
-    if (DO_C1) {
-        // colour 1, row i-1: neighbours new colour-0 rows i-2, i-1, i
+    const Vec<D> new0 = row_update<KIND, 2, D, P>(st.own0, st.q1b, side0, st.q1a, st.q1d, nullptr, nullptr,
+                                                  g0, 0u, a.t, ks, lut, thr_up, thr_down, STORE0, o);
+    if constexpr (STORE0) stv<D>(D0, (uint64_t)yi * rowb + cb, new0);
+    const Vec<D> q0 = prepv<KIND, D>(new0);
+    if constexpr (DO_C1) {
+        // colour 1, row i-1 (parity of i as well): neighbours new colour-0 rows i-2, i-1, i
         const uint32_t ym = wrapr(i - 1, L);
-        const uint32_t x1 = shift_in<XW>(st.n0b.w[D - 1], st.n0b.w[0], p, ln, e1);
+        const uint32_t x1 = shift_in<XW, P>(st.q0b.w[D - 1], st.q0b.w[0], ln, e1);
         uint32_t side1[D];
-        side_words<D>(st.n0b, x1, p, side1);
+        side_words<D, P>(st.q0b, x1, side1);
         const uint32_t g1 = ym * rg.ncols + D * ln.pos;
-        const Vec<D> new1 = row_update<KIND, 2, D>(st.c1a, st.n0b, side1, st.n0a, new0, nullptr, nullptr, p,
-                                                   g1, 1u, a.t, ks, lut, thr_up, thr_down, true, true, o);
+        const Vec<D> new1 = row_update<KIND, 2, D, P>(st.c1a, st.q0b, side1, st.q0a, q0, nullptr, nullptr, g1,
+                                                      1u, a.t, ks, lut, thr_up, thr_down, true, o);
         stv<D>(D1, (uint64_t)ym * rowb + cb, new1);
-        words_all += D;
-        words_c1 += D;
     }
     st.c1a = st.c1b;
     st.c1b = st.c1d;
-    st.c1d = st.c1n;
-    st.own0 = st.own0n;
-    st.n0a = st.n0b;
-    st.n0b = new0;
+    st.q1a = st.q1b;
+    st.q1b = st.q1d;
+    if constexpr (PREF) {
+        st.c1d = st.c1n;
+        st.q1d = prepv<KIND, D>(st.c1n);
+        st.own0 = st.own0n;
+    }
+    st.q0a = st.q0b;
+    st.q0b = q0;
+}
+
+template <int KIND, int D, bool XW, bool DO_C1, bool STORE0, bool PREF>
+__device__ __forceinline__ void fused_step_p(int i, FusedState<KIND, D>& st, const RowGeom& rg,
+                                             const Lanes& ln, const uint8_t* S0, const uint8_t* S1,
+                                             uint8_t* D0, uint8_t* D1, uint32_t (&xch)[2][16][4],
+                                             uint32_t& buf, const SweepArgs& a, const PhiloxKey& ks,
+                                             const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o)
+{
+    // row parity of i (L is even, so wrapping keeps it)
+    if ((i & 1) == 0)
+        fused_step<KIND, D, XW, 0, DO_C1, STORE0, PREF>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                         thr_up, thr_down, o);
+    else
+        fused_step<KIND, D, XW, 1, DO_C1, STORE0, PREF>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                         thr_up, thr_down, o);
 }
 
 template <int KIND, int D, bool XW>
@@ -528,8 +603,7 @@ __global__ void __launch_bounds__(1024) k_row_fused(SweepArgs a, RowGeom rg, con
     build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down);
     __syncthreads();
 
-    Obs o = {0, 0, 0, 0};
-    int32_t words_all = 0, words_c1 = 0;
+    Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, XW);
     const uint32_t item = row_item(rg, XW, ln);
     if (item < rg.nitems) {
@@ -539,26 +613,32 @@ __global__ void __launch_bounds__(1024) k_row_fused(SweepArgs a, RowGeom rg, con
         const int y0 = (int)(item * rg.H);
         const int y1 = min(y0 + (int)rg.H, (int)L);
         const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-        FusedState<KIND, D, XW> st;
+        FusedState<KIND, D> st;
         st.c1a = ldv<D>(S1, (uint64_t)wrapr(y0 - 2, L) * rowb + cb);
         st.c1b = ldv<D>(S1, (uint64_t)wrapr(y0 - 1, L) * rowb + cb);
         st.c1d = ldv<D>(S1, (uint64_t)wrapr(y0, L) * rowb + cb);
+        st.q1a = prepv<KIND, D>(st.c1a);
+        st.q1b = prepv<KIND, D>(st.c1b);
+        st.q1d = prepv<KIND, D>(st.c1d);
         st.own0 = ldv<D>(S0, (uint64_t)wrapr(y0 - 1, L) * rowb + cb);
 #pragma unroll
-        for (int d = 0; d < D; ++d) st.n0a.w[d] = st.n0b.w[d] = 0u;
+        for (int d = 0; d < D; ++d) st.q0a.w[d] = st.q0b.w[d] = 0u;
         uint32_t buf = 0;
-        fused_step<KIND, D, XW, false, false>(y0 - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
-                                              thr_up, thr_down, o, words_all, words_c1);
-        fused_step<KIND, D, XW, false, true>(y0, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut, thr_up,
-                                             thr_down, o, words_all, words_c1);
+        // halo row y0-1 (colour 0 only, not stored), first row y0 (colour 0
+        // only), rows y0+1 .. y1-1, halo row y1 (colour 1 of row y1-1 only)
+        fused_step_p<KIND, D, XW, false, false, true>(y0 - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks,
+                                                      lut, thr_up, thr_down, o);
+        fused_step_p<KIND, D, XW, false, true, true>(y0, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                     thr_up, thr_down, o);
         for (int i = y0 + 1; i < y1; ++i)
-            fused_step<KIND, D, XW, true, true>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
-                                                thr_up, thr_down, o, words_all, words_c1);
-        fused_step<KIND, D, XW, true, false>(y1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut, thr_up,
-                                             thr_down, o, words_all, words_c1);
+            fused_step_p<KIND, D, XW, true, true, true>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                        thr_up, thr_down, o);
+        fused_step_p<KIND, D, XW, true, false, false>(y1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                      thr_up, thr_down, o);
     }
-    finish_obs<KIND, 2>(o, words_all, words_c1);
-    block_accumulate(o.bond, o.mag, o.acc, o.unfl, a.acc);
+    int32_t bond, mag, acc, unfl;
+    finish_obs<KIND, 2>(o, bond, mag, acc, unfl);
+    block_accumulate(bond, mag, acc, unfl, a.acc);
 }
 
 // ---- host side ----------------------------------------------------------------

@@ -163,9 +163,16 @@ struct sl_lattice {
     sl_launch launch;
     uint64_t table[kMaxLut];
     size_t table_n;
+    sl_record* stage;  // pinned host staging for record readback (record_capacity)
 };
 
 namespace {
+
+void release(sl_lattice* h)
+{
+    if (h->stage) (void)hipHostFree(h->stage);
+    delete h;
+}
 
 SweepArgs args_of(const sl_lattice* h)
 {
@@ -338,13 +345,19 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
     h->cur = 0;
     h->table_n = build_table(params, h->table);
     h->launch = auto_launch(h);
-
-    hipError_t e = hipMemcpyAsync(h->base + lay.off_lut, h->table, h->table_n * sizeof(uint64_t),
+    h->stage = nullptr;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->stage),
+                                 params->record_capacity * sizeof(sl_record), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "create: pinned record staging");
+    }
+    e = hipMemcpyAsync(h->base + lay.off_lut, h->table, h->table_n * sizeof(uint64_t),
                                   hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = launch_fill_u64(slot_ptr(h, 0), params->record_capacity * kSlotWords, h->stream);
     if (e != hipSuccess) {
-        delete h;
+        release(h);
         return hip_fail(e, "create: table upload / ring clear");
     }
     SweepArgs a = args_of(h);
@@ -356,19 +369,19 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
                         (uint32_t)(bern >> 32), h->stream);
     }
     if (e != hipSuccess) {
-        delete h;
+        release(h);
         return hip_fail(e, "create: initial state");
     }
     st = enqueue_observe(h, 0);
     if (st != SL_OK) {
-        delete h;
+        release(h);
         return st;
     }
     h->pending = 1;
     // the table upload reads h->table; keep it alive until the copy is done
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
-        delete h;
+        release(h);
         return hip_fail(e, "create: synchronise");
     }
     *out = h;
@@ -466,9 +479,10 @@ sl_status sl_measure(sl_lattice* h, sl_record* out, size_t cap, size_t* n_out)
     hipError_t e = launch_fold(slot_ptr(h, 0), dev_out, n, h->first_t,
                                h->params.model == SL_ISING ? 1 : 0, h->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(out, dev_out, n * sizeof(sl_record), hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->stage, dev_out, n * sizeof(sl_record), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "measure");
+    std::memcpy(out, h->stage, n * sizeof(sl_record));
     static_assert(sizeof(sl_record) == kRecordWords * sizeof(int64_t), "record layout");
     h->first_t += n;
     h->pending = 0;
@@ -508,7 +522,7 @@ sl_status sl_destroy(sl_lattice* h)
 {
     if (!h) return fail(SL_E_INVALID, "NULL lattice");
     hipError_t e = hipStreamSynchronize(h->stream);
-    delete h;
+    release(h);
     if (e != hipSuccess) return hip_fail(e, "destroy: synchronise");
     return SL_OK;
 }
