@@ -34,13 +34,11 @@ struct Words4 {
 };
 
 // a ^ b ^ c in one VALU instruction (gfx950 three-input bitwise op, truth
-// table 0x96).  The third operand is wave-uniform (a round key) and stays in
-// a scalar register.  Not volatile: the compiler may schedule or drop it.
+// table 0x96); the round key operand is wave-uniform and stays in a scalar
+// register.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
-    uint32_t d;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(c));
-    return d;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 // Counter (c0, c1, c2, c3) -> four uniform 32-bit words.  Rounds 0 and 1 are
