@@ -28,6 +28,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
+KERNEL_SOURCES = ("kernels_row.hip", "site_update.hpp", "philox.hpp", "spinlat_internal.h")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE profile,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(workload)
+    if not entry:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1209_0296_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return entry["bytes_per_launch"] if h.hexdigest() == entry["sources_sha256"] else None
 
 
 def _lattice(S, cfg, T=None, record_capacity=4096):
@@ -145,6 +164,7 @@ def main():
               flush=True)
 
     roof = dict(main_res["roofline"])
+    roof["traffic"] = measured_traffic("ising2d_L8192")
     line = {
         "metric": "flip attempts/s at 2D L=8192 (% HBM peak)",
         "value": main_res["attempts_per_s"],
