@@ -28,7 +28,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
-KERNEL_SOURCES = ("kernels_row.hip", "site_update.hpp", "philox.hpp", "spinlat_internal.h")
+KERNEL_SOURCES = ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
+                  "spinlat_internal.h")
 
 
 def measured_traffic(workload):

@@ -176,6 +176,75 @@ sl_status sl_destroy(sl_lattice* lat);
 sl_status sl_record_observables(const sl_params* params, const sl_record* records, size_t n,
                                 double* E, double* M, double* P);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices ("jobs") of uneven size, model,
+ * temperature and seed advanced by shared launches (one launch per colour and
+ * per class of jobs with the same model kind, dimension and words per lane).
+ * Each job follows exactly the sweep of a lattice created alone with the same
+ * parameters: its lattice and records are identical alone and in any mix,
+ * because its random numbers depend only on its seed, sweep index and site.
+ *
+ * The caller owns one device arena; the batch keeps its job table and work
+ * lists at the start of it and places every job's lattice and record ring in
+ * the rest.  A job is admitted only if its footprint (sl_batch_job_bytes) fits
+ * in the free arena space; removing a job returns its space.
+ * Batched jobs need L % 8 == 0, a colour row of at most 256 four-byte words
+ * (L <= 2048) and, for spin-1/2, every threshold >= 1.
+ * ------------------------------------------------------------------------- */
+typedef struct sl_batch sl_batch;
+
+typedef struct sl_batch_config {
+    uint32_t abi_version;     /* SL_ABI_VERSION */
+    uint32_t max_jobs;        /* size of the job table */
+    uint32_t record_capacity; /* records each job holds between measurements (>= 2) */
+    int32_t tile_rows;        /* rows per strip of the batched kernels (0: default) */
+    uint64_t max_workgroups;  /* size of the work list (0: default 1 << 20) */
+} sl_batch_config;
+
+/* Arena bytes a job with these parameters occupies (host-only, pure). */
+sl_status sl_batch_job_bytes(const sl_params* params, const sl_batch_config* cfg, size_t* bytes);
+
+/* Arena bytes the batch itself needs before any job (host-only, pure). */
+sl_status sl_batch_base_bytes(const sl_batch_config* cfg, size_t* bytes);
+
+/* Bind the caller's device arena (256-byte aligned) and stream. */
+sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t arena_bytes,
+                          void* hip_stream, sl_batch** out);
+
+/* Admit a job (params as for sl_create_lattice, record_capacity ignored) that
+ * is to run `sweeps` sweeps in total.  Initialises its lattice and record r_0
+ * on the stream.  SL_E_BUFFER: not enough free arena (nothing changed);
+ * SL_E_STATE: job table full; SL_E_UNSUPPORTED: shape not batchable. */
+sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, uint32_t* job_id);
+
+/* Enqueue up to n sweeps of every job that has sweeps left and room in its
+ * record ring; jobs stop individually.  Synchronises the stream once (to
+ * upload the per-job counters), then enqueues asynchronously. */
+sl_status sl_batch_sweep(sl_batch* b, uint64_t n);
+
+/* Per-job counters: sweeps done, sweeps left, unread records. */
+sl_status sl_batch_job_status(const sl_batch* b, uint32_t job_id, uint64_t* done,
+                              uint64_t* remaining, uint64_t* pending);
+
+/* Synchronise and move the job's unread records to out (host memory). */
+sl_status sl_batch_measure(sl_batch* b, uint32_t job_id, sl_record* out, size_t cap,
+                           size_t* n_out);
+
+/* Synchronise and move the unread records of every job to out (host memory)
+ * with one fold launch and one copy: the records of a job are contiguous and
+ * in sweep order, job_of[i] names the job of out[i].  SL_E_BUFFER (nothing
+ * drained) if cap is smaller than the total. */
+sl_status sl_batch_drain(sl_batch* b, sl_record* out, uint32_t* job_of, size_t cap, size_t* n_out);
+
+/* Enqueue a copy of a job's lattice, natural order, into device_out. */
+sl_status sl_batch_copy_spins(sl_batch* b, uint32_t job_id, int8_t* device_out, size_t n);
+
+/* Retire a job: synchronises, frees its arena space; unread records are lost. */
+sl_status sl_batch_remove(sl_batch* b, uint32_t job_id);
+
+/* Release the batch (never frees the arena).  Synchronises. */
+sl_status sl_batch_destroy(sl_batch* b);
+
 const char* sl_status_str(sl_status status);
 const char* sl_last_error(void);
 

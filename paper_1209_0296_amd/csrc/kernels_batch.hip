@@ -1,0 +1,154 @@
+// kernels_batch.hip -- one launch advances a half-sweep of many independent
+// lattices (jobs) of uneven size, model, temperature and seed.
+//
+// Every job keeps its own lattice, threshold table, Philox key, sweep index
+// and record ring; the launch reads them from a device job table.  A work
+// table lists, for one class of jobs (same model kind, dimension and words
+// per lane), the workgroups to run as (job, first item) pairs, so a
+// workgroup only ever touches one job and its reduction goes to that job's
+// record.  Because the random numbers depend on (seed, sweep, site) only, a
+// job's lattice and records are the same alone and in any mix.
+//
+// Per-job counters {t, record slot, sweeps left in this call} live in a
+// small device array that the host uploads before a batch of sweeps; after
+// each sweep k_batch_advance moves them on, so the same sequence of launches
+// serves every sweep and no argument changes between sweeps.
+#include "row_device.hpp"
+#include "batch_internal.h"
+
+namespace spinlat {
+
+namespace {
+
+template <int KIND, int DIM, int D>
+__global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ dyn,
+                                                    const BatchWG* __restrict__ wgs, uint32_t colour)
+{
+    __shared__ RowLuts lut;
+    __shared__ uint32_t xch[2][16][2];
+    const BatchWG w = wgs[blockIdx.x];
+    const uint32_t* dj = dyn + kDynWords * w.job;
+    const uint32_t remaining = dj[2];
+    if (remaining == 0) return;  // whole workgroup: this job has no sweep left in this call
+    const BatchJob& J = jobs[w.job];
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
+    __syncthreads();
+
+    SweepArgs a{};
+    a.col[0] = J.col[0];
+    a.col[1] = J.col[1];
+    a.key0 = J.key0;
+    a.key1 = J.key1;
+    a.t = dj[0];
+    a.colour = colour;
+    const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
+    Obs o = {0, 0, 0, 0, 0};
+    const Lanes ln = lanes_of(rg, false);
+    const uint32_t slot_in_wave = ln.lane / rg.R;
+    const uint32_t item = slot_in_wave < rg.slots
+                              ? w.item_base + ln.wave * rg.slots + slot_in_wave
+                              : 0xFFFFFFFFu;
+    half_item<KIND, DIM, D, false>(a, rg, item, ln, lut, xch, thr_up, thr_down, o);
+    int32_t bond, mag, acc, unfl;
+    finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
+    block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
+}
+
+__global__ void __launch_bounds__(256) k_batch_advance(uint32_t* dyn, uint32_t njobs)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= njobs) return;
+    uint32_t* d = dyn + kDynWords * j;
+    if (d[2] > 0) {
+        d[0] += 1;  // sweep index
+        d[1] += 1;  // record slot
+        d[2] -= 1;  // sweeps left
+    }
+}
+
+// One workgroup per job: sum the sub-slots of each unread record, write
+// {t, bond_sum, mag, accepted, unflipped} and clear the accumulators.
+__global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict__ tab, int64_t* out)
+{
+    const BatchFold f = tab[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < f.n; i += 256) {
+        unsigned long long* slot = f.ring + (uint64_t)i * kSlotWords;
+        int64_t sum[kQ] = {0, 0, 0, 0};
+        for (int s = 0; s < kSub; ++s)
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                sum[q] += (int64_t)slot[s * kQ + q];
+                slot[s * kQ + q] = 0ull;
+            }
+        int64_t* o = out + (f.out_off + i) * kRecordWords;
+        o[0] = (int64_t)(f.first_t + i);
+        o[1] = sum[0];
+        o[2] = sum[1];
+        o[3] = sum[2];
+        o[4] = f.ising ? -1 : sum[3];
+    }
+}
+
+template <int KIND, int DIM>
+hipError_t launch_class_d(int D, const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
+                          uint32_t colour, hipStream_t s)
+{
+    if (D == 4)
+        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 4>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
+    else if (D == 2)
+        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 2>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
+    else
+        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 1>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool batch_geom(const Geom& g, int H, RowGeomHost& out)
+{
+    // widest D whose row group fits one wave (the batched kernel has no
+    // cross-wave exchange)
+    for (int D : {4, 2, 1}) {
+        RowGeom rg;
+        if (!make_row_geom(g, H, D, false, rg)) continue;
+        if (rg.R > 64) continue;
+        static_assert(sizeof(RowGeom) <= sizeof(out.bytes), "RowGeom storage");
+        __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
+        out.D = D;
+        out.nitems = rg.nitems;
+        out.items_per_wg = 4 * rg.slots;
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,
+                              const BatchWG* wgs, uint32_t nwg, uint32_t colour, hipStream_t s)
+{
+    if (nwg == 0) return hipSuccess;
+    if (kind == KIND_NE) return launch_class_d<KIND_NE, 2>(D, jobs, dyn, wgs, nwg, colour, s);
+    if (dim == 2) {
+        if (kind == KIND_ISING_HALF) return launch_class_d<KIND_ISING_HALF, 2>(D, jobs, dyn, wgs, nwg, colour, s);
+        return launch_class_d<KIND_ISING_ONE, 2>(D, jobs, dyn, wgs, nwg, colour, s);
+    }
+    if (kind == KIND_ISING_HALF) return launch_class_d<KIND_ISING_HALF, 3>(D, jobs, dyn, wgs, nwg, colour, s);
+    return launch_class_d<KIND_ISING_ONE, 3>(D, jobs, dyn, wgs, nwg, colour, s);
+}
+
+hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* out, hipStream_t s)
+{
+    if (nentries == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_fold, dim3(nentries), dim3(256), 0, s, tab, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(uint32_t* dyn, uint32_t njobs, hipStream_t s)
+{
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_advance, dim3((njobs + 255) / 256), dim3(256), 0, s, dyn, njobs);
+    return hipGetLastError();
+}
+
+}  // namespace spinlat

@@ -15,13 +15,17 @@
 #include <new>
 
 #include "../../include/spinlat.h"
+#include "host_common.h"
 #include "spinlat_internal.h"
 
 using namespace spinlat;
 
-namespace {
+namespace spinlat {
+namespace host {
 
 thread_local char g_err[512] = "";
+
+const char* last_error() { return g_err; }
 
 sl_status fail(sl_status st, const char* fmt, ...)
 {
@@ -36,21 +40,6 @@ sl_status hip_fail(hipError_t e, const char* what)
 {
     return fail(SL_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-constexpr size_t kAlign = 256;
-inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Layout {
-    uint64_t nsites;   // L^dim
-    uint64_t nh;       // per colour
-    size_t col_bytes;  // one colour array, rounded to kAlign
-    size_t off_col[2][2];  // [copy][colour]: two copies of the lattice (fused sweeps
-                           // read one and write the other)
-    size_t off_acc;    // accumulators [capacity][kSub][kQ] int64
-    size_t off_out;    // folded records [capacity][5] int64
-    size_t off_lut;    // threshold table, kMaxLut u64
-    size_t total;
-};
 
 int kind_of(const sl_params* p)
 {
@@ -148,7 +137,10 @@ size_t build_table(const sl_params* p, uint64_t* out)
     return n;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace spinlat
+
+using namespace spinlat::host;
 
 struct sl_lattice {
     sl_params params;

@@ -30,7 +30,9 @@ EXPORTS = (
     "sl_query_bytes", "sl_threshold_table", "sl_create_lattice", "sl_set_launch",
     "sl_get_launch", "sl_sweep", "sl_measure", "sl_status_counts", "sl_copy_spins",
     "sl_reset_persistence", "sl_destroy", "sl_status_str", "sl_last_error",
-    "sl_record_observables",
+    "sl_record_observables", "sl_batch_job_bytes", "sl_batch_base_bytes", "sl_batch_create",
+    "sl_batch_add", "sl_batch_sweep", "sl_batch_job_status", "sl_batch_measure",
+    "sl_batch_copy_spins", "sl_batch_remove", "sl_batch_destroy", "sl_batch_drain",
 )
 
 
@@ -53,6 +55,12 @@ class CParams(ctypes.Structure):
 class CRecord(ctypes.Structure):
     _fields_ = [("t", ctypes.c_uint64), ("bond_sum", ctypes.c_int64), ("mag", ctypes.c_int64),
                 ("accepted", ctypes.c_int64), ("unflipped", ctypes.c_int64)]
+
+
+class CBatchConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("max_jobs", ctypes.c_uint32),
+                ("record_capacity", ctypes.c_uint32), ("tile_rows", ctypes.c_int32),
+                ("max_workgroups", ctypes.c_uint64)]
 
 
 class CLaunch(ctypes.Structure):
@@ -93,6 +101,20 @@ def lib():
     L.sl_last_error.restype = ctypes.c_char_p
     L.sl_record_observables.argtypes = [P, ctypes.c_void_p, sz, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]
+    B, BC = ctypes.c_void_p, ctypes.POINTER(CBatchConfig)
+    L.sl_batch_job_bytes.argtypes = [P, BC, ctypes.POINTER(sz)]
+    L.sl_batch_base_bytes.argtypes = [BC, ctypes.POINTER(sz)]
+    L.sl_batch_create.argtypes = [BC, ctypes.c_void_p, sz, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.sl_batch_add.argtypes = [B, P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
+    L.sl_batch_sweep.argtypes = [B, ctypes.c_uint64]
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.sl_batch_job_status.argtypes = [B, ctypes.c_uint32, u64p, u64p, u64p]
+    L.sl_batch_measure.argtypes = [B, ctypes.c_uint32, ctypes.c_void_p, sz, ctypes.POINTER(sz)]
+    L.sl_batch_copy_spins.argtypes = [B, ctypes.c_uint32, ctypes.c_void_p, sz]
+    L.sl_batch_drain.argtypes = [B, ctypes.c_void_p, ctypes.c_void_p, sz, ctypes.POINTER(sz)]
+    L.sl_batch_remove.argtypes = [B, ctypes.c_uint32]
+    L.sl_batch_destroy.argtypes = [B]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sl_status_str", "sl_last_error"):
@@ -264,3 +286,127 @@ class Lattice:
 def records_to_array(records: np.ndarray) -> np.ndarray:
     """Structured records -> (n, 5) int64 array {t, bond_sum, mag, accepted, unflipped}."""
     return np.stack([records[f].astype(np.int64) for f in RECORD_DTYPE.names], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent lattices sharing launches
+
+def batch_config(max_jobs: int = 1024, record_capacity: int = 256, tile_rows: int = 0,
+                 max_workgroups: int = 0) -> CBatchConfig:
+    return CBatchConfig(ABI_VERSION, max_jobs, record_capacity, tile_rows, max_workgroups)
+
+
+def batch_job_bytes(p: Params, cfg: CBatchConfig) -> int:
+    n = ctypes.c_size_t()
+    cp = p.c_struct(1 if p.init == INIT_BUFFER else 0)
+    _check(lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def batch_base_bytes(cfg: CBatchConfig) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sl_batch_base_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+class Batch:
+    """Many lattices (jobs) resident in one device arena, advanced together.
+
+    ``add`` admits a job if its footprint fits the free arena space (returns
+    None otherwise), ``sweep(n)`` runs up to n sweeps of every job with sweeps
+    left, ``measure(job)`` drains a job's records.
+    """
+
+    def __init__(self, arena_bytes: int, max_jobs: int = 1024, record_capacity: int = 256,
+                 tile_rows: int = 0, device="cuda", stream=None, max_workgroups: int = 0):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cfg = batch_config(max_jobs, record_capacity, tile_rows, max_workgroups)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self._init_refs = {}
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().sl_batch_create(ctypes.byref(self.cfg), self.arena.data_ptr(),
+                                         self.arena.numel(), self.stream.cuda_stream,
+                                         ctypes.byref(h)))
+        self._h = h
+        self.params = {}
+
+    def add(self, p: Params, sweeps: int, init_spins=None):
+        """Job id, or None when the arena has no room for it."""
+        torch = self._torch
+        ptr = 0
+        if p.init == INIT_BUFFER:
+            t = init_spins.to(device=self.device, dtype=torch.int8).contiguous()
+            ptr = t.data_ptr()
+        cp = p.c_struct(ptr)
+        jid = ctypes.c_uint32()
+        st = lib().sl_batch_add(self._h, ctypes.byref(cp), int(sweeps), ctypes.byref(jid))
+        if st == 3:
+            return None
+        _check(st)
+        self.params[jid.value] = p
+        return jid.value
+
+    def sweep(self, n: int) -> None:
+        _check(lib().sl_batch_sweep(self._h, int(n)))
+
+    def status(self, job: int):
+        d, r, p = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sl_batch_job_status(self._h, job, ctypes.byref(d), ctypes.byref(r),
+                                         ctypes.byref(p)))
+        return d.value, r.value, p.value
+
+    def measure(self, job: int) -> np.ndarray:
+        _, _, pending = self.status(job)
+        out = np.zeros(max(pending, 1), dtype=RECORD_DTYPE)
+        n = ctypes.c_size_t()
+        _check(lib().sl_batch_measure(self._h, job, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out[: n.value]
+
+    def drain(self):
+        """All jobs' unread records: {job id: (n, 5) int64 array}."""
+        cap = self.cfg.max_jobs * self.cfg.record_capacity
+        if not hasattr(self, "_drain_buf") or self._drain_buf.size < cap:
+            self._drain_buf = np.zeros(cap, dtype=RECORD_DTYPE)
+            self._drain_job = np.zeros(cap, dtype=np.uint32)
+        n = ctypes.c_size_t()
+        _check(lib().sl_batch_drain(self._h, self._drain_buf.ctypes.data,
+                                    self._drain_job.ctypes.data, cap, ctypes.byref(n)))
+        n = n.value
+        recs = records_to_array(self._drain_buf[:n])
+        jobs = self._drain_job[:n]
+        out = {}
+        if n:
+            cuts = np.flatnonzero(np.diff(jobs)) + 1
+            starts = np.concatenate([[0], cuts])
+            ends = np.concatenate([cuts, [n]])
+            for a, e in zip(starts, ends):
+                out[int(jobs[a])] = recs[a:e]
+        return out
+
+    def spins(self, job: int) -> np.ndarray:
+        torch = self._torch
+        p = self.params[job]
+        out = torch.empty(p.nsites, dtype=torch.int8, device=self.device)
+        _check(lib().sl_batch_copy_spins(self._h, job, out.data_ptr(), out.numel()))
+        self.stream.synchronize()
+        return out.cpu().numpy().reshape(p.shape)
+
+    def remove(self, job: int) -> None:
+        _check(lib().sl_batch_remove(self._h, job))
+        self.params.pop(job, None)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib().sl_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -101,3 +101,13 @@ def test_record_observables():
 def test_status_strings():
     for code, name in B.STATUS.items():
         assert S.lib().sl_status_str(code).decode() == name
+
+
+def test_batch_rejects_unbatchable_shapes():
+    cfg = S.batch_config(max_jobs=4, record_capacity=8)
+    with pytest.raises(S.SpinlatError) as e:
+        S.batch_job_bytes(S.Params(L=2056), cfg)  # 257-word colour rows
+    assert e.value.status == 2
+    with pytest.raises(S.SpinlatError) as e:
+        S.batch_job_bytes(S.Params(L=64, T=0.05), cfg)  # zero thresholds
+    assert e.value.status == 2

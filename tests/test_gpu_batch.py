@@ -1,0 +1,132 @@
+"""GPU parity of batched sweeps: every job of a mixed batch must reproduce,
+bit for bit, the oracle run of the same job alone (lattice and every record),
+whatever else shares its launches and whenever it was admitted."""
+import numpy as np
+import pytest
+
+import paper_1209_0296_amd as S
+from helpers import run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_jobs():
+    jobs = [
+        S.Params(L=64, T=2.269, init=S.INIT_COLD, seed=1),
+        S.Params(L=40, T=2.0, seed=2),                      # D = 1 rows
+        S.Params(L=136, two_s=2, T=1.7, seed=3),
+        S.Params(L=256, T=2.4, h=0.1, seed=4),              # 32-word rows, D = 4
+        S.Params(L=1024, T=2.269, seed=5),                  # 128-word rows, D = 2
+        S.Params(dim=3, L=16, T=4.5, seed=6),
+        S.Params(dim=3, L=24, two_s=2, T=3.2, seed=7),
+        S.Params(dim=3, L=64, T=4.0, J=0.9, seed=8),
+        S.Params(model=S.NORTH_EAST, L=72, c=0.2, seed=9),
+        S.Params(model=S.NORTH_EAST, L=128, c=0.1, seed=10),
+    ]
+    return jobs
+
+
+def _check_job(batch, jid, sp, recs, nsweeps):
+    o_s, o_r = run_oracle(sp, nsweeps)
+    np.testing.assert_array_equal(np.vstack(recs), o_r)
+    np.testing.assert_array_equal(batch.spins(jid), o_s)
+
+
+def test_mixed_batch_matches_each_job_alone():
+    jobs = _mixed_jobs()
+    b = S.Batch(arena_bytes=64 << 20, max_jobs=16, record_capacity=64)
+    ids = [b.add(p, sweeps=12) for p in jobs]
+    assert all(i is not None for i in ids)
+    recs = {i: [S.records_to_array(b.measure(i))] for i in ids}
+    b.sweep(5)
+    for i in ids:
+        recs[i].append(S.records_to_array(b.measure(i)))
+    b.sweep(100)  # every job stops at its own 12
+    for i, p in zip(ids, jobs):
+        assert b.status(i)[:2] == (12, 0)
+        recs[i].append(S.records_to_array(b.measure(i)))
+        _check_job(b, i, p, recs[i], 12)
+    b.close()
+
+
+def test_uneven_budgets_and_late_admission():
+    b = S.Batch(arena_bytes=32 << 20, max_jobs=8, record_capacity=16)
+    early = S.Params(L=128, T=2.3, seed=21)
+    ja = b.add(early, sweeps=30)
+    ra = [S.records_to_array(b.measure(ja))]
+    b.sweep(7)
+    late = S.Params(dim=3, L=32, two_s=2, T=3.0, seed=22)
+    jb = b.add(late, sweeps=9)
+    short = S.Params(L=64, T=1.9, seed=23)
+    jc = b.add(short, sweeps=3)
+    rb = [S.records_to_array(b.measure(jb))]
+    rc = [S.records_to_array(b.measure(jc))]
+    # the ring holds 16 records: sweep in chunks and drain between them
+    while any(b.status(j)[1] for j in (ja, jb, jc)):
+        b.sweep(10)
+        ra.append(S.records_to_array(b.measure(ja)))
+        rb.append(S.records_to_array(b.measure(jb)))
+        rc.append(S.records_to_array(b.measure(jc)))
+    _check_job(b, ja, early, ra, 30)
+    _check_job(b, jb, late, rb, 9)
+    _check_job(b, jc, short, rc, 3)
+    b.close()
+
+
+def test_admission_by_footprint_and_reuse():
+    cfg = S.batch_config(max_jobs=8, record_capacity=8)
+    p = S.Params(L=512, T=2.2, seed=31)
+    need = S.batch_job_bytes(p, cfg)
+    base = S.batch_base_bytes(cfg)
+    b = S.Batch(arena_bytes=base + 2 * need + 4096, max_jobs=8, record_capacity=8)
+    j1 = b.add(p, sweeps=4)
+    j2 = b.add(S.Params(L=512, T=2.5, seed=32), sweeps=4)
+    assert j1 is not None and j2 is not None
+    assert b.add(S.Params(L=512, T=2.0, seed=33), sweeps=4) is None  # no room: refused
+    r1 = [S.records_to_array(b.measure(j1))]
+    b.sweep(4)
+    r1.append(S.records_to_array(b.measure(j1)))
+    _check_job(b, j1, p, r1, 4)
+    b.remove(j1)
+    p3 = S.Params(L=512, T=2.0, seed=33)
+    j3 = b.add(p3, sweeps=4)  # fits again in the freed space
+    assert j3 is not None
+    r3 = [S.records_to_array(b.measure(j3))]
+    b.sweep(4)
+    r3.append(S.records_to_array(b.measure(j3)))
+    _check_job(b, j3, p3, r3, 4)
+    b.close()
+
+
+def test_batch_equals_standalone_lattice():
+    """Batched and standalone GPU runs of the same job agree (and with the oracle)."""
+    from helpers import run_gpu
+
+    p = S.Params(L=256, T=2.269, seed=41, record_capacity=32)
+    g_s, g_r = run_gpu(p, 20)
+    b = S.Batch(arena_bytes=16 << 20, max_jobs=4, record_capacity=32)
+    j = b.add(p, sweeps=20)
+    r = [S.records_to_array(b.measure(j))]
+    b.sweep(20)
+    r.append(S.records_to_array(b.measure(j)))
+    np.testing.assert_array_equal(np.vstack(r), g_r)
+    np.testing.assert_array_equal(b.spins(j), g_s)
+    b.close()
+
+
+def test_drain_collects_every_job():
+    """sl_batch_drain (one fold launch, one copy) gives each job's records."""
+    jobs = _mixed_jobs()
+    b = S.Batch(arena_bytes=64 << 20, max_jobs=16, record_capacity=8)
+    ids = [b.add(p, sweeps=10 + k) for k, p in enumerate(jobs)]
+    recs = {i: [] for i in ids}
+    while True:
+        got = b.drain()
+        for j, r in got.items():
+            recs[j].append(r)
+        if not any(b.status(i)[1] for i in ids):
+            break
+        b.sweep(7)
+    for i, p in zip(ids, jobs):
+        _check_job(b, i, p, recs[i], b.status(i)[0])
+    b.close()
