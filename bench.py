@@ -111,6 +111,41 @@ def cpu_baseline(cfg, sweeps, threads):
             "sample": f"{sweeps} sweeps of 2D L={cfg['L']} (records every sweep), {dt:.1f} s"}
 
 
+def served(args):
+    """Continuous batching of a Poisson stream of independent Ising jobs, and
+    the same first jobs as a closed batch, batched vs one run per launch."""
+    import numpy as np
+
+    from paper_1209_0296_amd.serve import Server, requests_from_workload, run_one_per_launch
+    from workloads import served_requests
+
+    reqs = requests_from_workload(served_requests(args.served_jobs, rate=args.served_rate))
+    arena = args.served_arena_mib << 20
+    srv = Server(arena, max_jobs=4096, chunk=64)
+    # warm-up: compile and load every batched kernel once
+    srv.run(requests_from_workload(served_requests(16, rate=1e9, seed=99, sweeps=(2, 4))),
+            realtime=False)
+    outcomes, stats = srv.run(reqs, realtime=True)
+    attempts = sum(r.params.nsites * r.sweeps for r in reqs)
+    out = {"workload": f"served_ising_{len(reqs)}", "arrival_rate_per_s": args.served_rate,
+           "arena_bytes": arena, "chunk_sweeps": 64, "jobs": stats["jobs"],
+           "jobs_per_s": stats["jobs_per_s"], "p50_latency_s": stats["p50_latency_s"],
+           "p99_latency_s": stats["p99_latency_s"], "makespan_s": stats["makespan_s"],
+           "attempts_per_s": attempts / stats["makespan_s"]}
+    k = min(args.compare_jobs, len(reqs))
+    if k:
+        sub = reqs[:k]
+        o_b, s_b = srv.run(sub, realtime=False)
+        o_1, s_1 = run_one_per_launch(sub, realtime=False)
+        same = all(np.array_equal(o_b[r.id].records, o_1[r.id].records) for r in sub)
+        out["vs_one_per_launch"] = {"jobs": k, "batched_jobs_per_s": s_b["jobs_per_s"],
+                                    "one_per_launch_jobs_per_s": s_1["jobs_per_s"],
+                                    "speedup": s_b["jobs_per_s"] / s_1["jobs_per_s"],
+                                    "identical_records": bool(same)}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +154,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D L=256 line")
     ap.add_argument("--cpu-sweeps", type=int, default=30)
+    ap.add_argument("--served-jobs", type=int, default=4096,
+                    help="jobs in the served Poisson stream (0: skip serving)")
+    ap.add_argument("--served-rate", type=float, default=1000.0, help="arrivals per second")
+    ap.add_argument("--served-arena-mib", type=int, default=512)
+    ap.add_argument("--compare-jobs", type=int, default=48,
+                    help="jobs served both batched and one run per launch (closed batch)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -157,6 +198,11 @@ def main():
             secondary.append({k: r[k] for k in ("workload", "attempts_per_s", "ms_per_step",
                                                  "sweep_kernels_ms_per_step", "launch")}
                              | {"roofline_frac": r["roofline"]["frac"]})
+    served_res = None
+    if args.served_jobs > 0:
+        served_res = served(args)
+        print(f"# served: {served_res['jobs_per_s']:.4g} jobs/s, p50 {served_res['p50_latency_s']:.3g} s, "
+              f"p99 {served_res['p99_latency_s']:.3g} s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
@@ -182,6 +228,7 @@ def main():
                             "algo_bytes_per_launch": roof["algo_bytes_per_launch"],
                             "algo_bytes_per_attempt": ALGO_BYTES_PER_ATTEMPT},
         "cpu_baseline": cpu,
+        "served": served_res,
         "secondary": secondary,
     }
     print(json.dumps(line), flush=True)

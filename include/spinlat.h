@@ -188,8 +188,9 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
  * lists at the start of it and places every job's lattice and record ring in
  * the rest.  A job is admitted only if its footprint (sl_batch_job_bytes) fits
  * in the free arena space; removing a job returns its space.
- * Batched jobs need L % 8 == 0, a colour row of at most 256 four-byte words
- * (L <= 2048) and, for spin-1/2, every threshold >= 1.
+ * Batched jobs need L % 8 == 0.  Jobs whose colour row splits into row groups
+ * of at most 64 lanes run the whole-row kernels, the others the column-window
+ * kernels (also spin-1/2 jobs with a zero threshold).
  * ------------------------------------------------------------------------- */
 typedef struct sl_batch sl_batch;
 
@@ -214,7 +215,7 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
 /* Admit a job (params as for sl_create_lattice, record_capacity ignored) that
  * is to run `sweeps` sweeps in total.  Initialises its lattice and record r_0
  * on the stream.  SL_E_BUFFER: not enough free arena (nothing changed);
- * SL_E_STATE: job table full; SL_E_UNSUPPORTED: shape not batchable. */
+ * SL_E_STATE: job table full; SL_E_UNSUPPORTED: L % 8 != 0. */
 sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, uint32_t* job_id);
 
 /* Enqueue up to n sweeps of every job that has sweeps left and room in its

@@ -194,16 +194,13 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     sl_status st = validate(p);
     if (st != SL_OK) return st;
     *foot = job_foot(p, cfg->record_capacity);
-    const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim);
-    if (!batch_geom(geom_of(p, foot->nh), H, *geom))
-        return fail(SL_E_UNSUPPORTED, "L = %d does not fit the batched kernels (colour row of at most "
-                    "256 words)", p->L);
     *table_n = build_table(p, table);
-    if (kind_of(p) == KIND_ISING_HALF)
-        for (size_t i = 0; i < *table_n; ++i)
-            if (table[i] == 0)
-                return fail(SL_E_UNSUPPORTED, "a threshold is 0 (T too low) for the batched spin-1/2 "
-                            "kernels; use a standalone lattice");
+    bool lut32 = true;
+    for (size_t i = 0; i < *table_n; ++i)
+        if (table[i] == 0) lut32 = false;
+    const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim);
+    if (!batch_geom(geom_of(p, foot->nh), H, lut32 || kind_of(p) != KIND_ISING_HALF, *geom))
+        return fail(SL_E_UNSUPPORTED, "L = %d does not fit the batched kernels", p->L);
     return SL_OK;
 }
 
@@ -382,7 +379,7 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     uint64_t nwg = 0;
     for (int kind : {KIND_ISING_HALF, KIND_ISING_ONE, KIND_NE})
         for (int dim : {2, 3})
-            for (int D : {4, 2, 1}) {
+            for (int D : {4, 2, 1, 0}) {
                 Cls c{kind, dim, D, (uint32_t)nwg, 0};
                 for (uint32_t j = 0; j < top; ++j) {
                     const JobHost& J = b->jobs[j];

@@ -34,14 +34,15 @@ struct BatchFold {
 
 struct RowGeomHost {
     uint32_t bytes[16];      // RowGeom as the kernels see it
-    int D;                   // words per lane
+    int D;                   // words per lane (0: column-window kernel)
     uint32_t nitems;         // items of one half-sweep
     uint32_t items_per_wg;   // items one workgroup of 256 lanes covers
 };
 
-// Geometry of a job for the batched kernels (row groups within one wave);
-// false if the colour row does not fit one wave.
-bool batch_geom(const Geom& g, int H, RowGeomHost& out);
+// Geometry of a job for the batched kernels: whole-row groups within one wave
+// (D = 1, 2, 4) when the row fits and the 32-bit spin-1/2 table applies, else
+// 64-lane column windows (D = 0).
+bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out);
 hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,
                               const BatchWG* wgs, uint32_t nwg, uint32_t colour, hipStream_t s);
 hipError_t launch_batch_advance(uint32_t* dyn, uint32_t njobs, hipStream_t s);

@@ -14,9 +14,12 @@
 // each sweep k_batch_advance moves them on, so the same sequence of launches
 // serves every sweep and no argument changes between sweeps.
 #include "row_device.hpp"
+#include "stream_device.hpp"
 #include "batch_internal.h"
 
 namespace spinlat {
+
+using namespace rowk;
 
 namespace {
 
@@ -54,6 +57,37 @@ __global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
     block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
+}
+
+// Jobs whose colour row does not fit one wave (or whose spin-1/2 table has a
+// zero threshold): 64-lane column windows with edge loads (any L % 8 == 0).
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(256) k_batch_window(const BatchJob* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ dyn,
+                                                      const BatchWG* __restrict__ wgs, uint32_t colour)
+{
+    __shared__ streamk::Luts lut;
+    const BatchWG w = wgs[blockIdx.x];
+    const uint32_t* dj = dyn + kDynWords * w.job;
+    if (dj[2] == 0) return;  // whole workgroup: no sweep left for this job
+    const BatchJob& J = jobs[w.job];
+    uint64_t thr_up, thr_down;
+    streamk::build_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
+    __syncthreads();
+
+    SweepArgs a{};
+    a.col[0] = J.col[0];
+    a.col[1] = J.col[1];
+    a.key0 = J.key0;
+    a.key1 = J.key1;
+    a.t = dj[0];
+    a.colour = colour;
+    const streamk::StreamGeom sg = *reinterpret_cast<const streamk::StreamGeom*>(J.rg_words);
+    streamk::Obs o = {0, 0, 0, 0};
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t item = w.item_base + (threadIdx.x >> 6) * sg.G + lane / sg.W;
+    streamk::stream_half_item<KIND, DIM>(a, sg, item, lut, thr_up, thr_down, o);
+    block_accumulate(o.bond, o.mag, o.acc, o.unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
 }
 
 __global__ void __launch_bounds__(256) k_batch_advance(uint32_t* dyn, uint32_t njobs)
@@ -95,7 +129,9 @@ template <int KIND, int DIM>
 hipError_t launch_class_d(int D, const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
                           uint32_t colour, hipStream_t s)
 {
-    if (D == 4)
+    if (D == 0)
+        hipLaunchKernelGGL((k_batch_window<KIND, DIM>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
+    else if (D == 4)
         hipLaunchKernelGGL((k_batch_half<KIND, DIM, 4>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
     else if (D == 2)
         hipLaunchKernelGGL((k_batch_half<KIND, DIM, 2>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
@@ -106,11 +142,12 @@ hipError_t launch_class_d(int D, const BatchJob* jobs, const uint32_t* dyn, cons
 
 }  // namespace
 
-bool batch_geom(const Geom& g, int H, RowGeomHost& out)
+bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out)
 {
-    // widest D whose row group fits one wave (the batched kernel has no
-    // cross-wave exchange)
+    // widest D whose row group fits one wave (the whole-row batched kernel
+    // has no cross-wave exchange) ...
     for (int D : {4, 2, 1}) {
+        if (!lut32_ok) break;
         RowGeom rg;
         if (!make_row_geom(g, H, D, false, rg)) continue;
         if (rg.R > 64) continue;
@@ -121,7 +158,15 @@ bool batch_geom(const Geom& g, int H, RowGeomHost& out)
         out.items_per_wg = 4 * rg.slots;
         return true;
     }
-    return false;
+    // ... else column windows (D = 0)
+    if (g.Lh % 4) return false;
+    const streamk::StreamGeom sg = streamk::make_geom(g, H, false);
+    static_assert(sizeof(streamk::StreamGeom) <= sizeof(out.bytes), "StreamGeom storage");
+    __builtin_memcpy(out.bytes, &sg, sizeof(sg));
+    out.D = 0;
+    out.nitems = sg.nitems;
+    out.items_per_wg = 4 * sg.G;
+    return true;
 }
 
 hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,

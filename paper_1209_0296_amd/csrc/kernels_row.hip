@@ -4,6 +4,8 @@
 
 namespace spinlat {
 
+using namespace rowk;
+
 namespace {
 
 template <int KIND, int DIM, int D, bool XW>

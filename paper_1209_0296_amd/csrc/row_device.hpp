@@ -34,7 +34,7 @@
 
 namespace spinlat {
 
-namespace {
+namespace rowk {
 
 constexpr uint32_t M4 = 0x04040404u;
 
@@ -614,6 +614,6 @@ inline bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg)
     return true;
 }
 
-}  // namespace
+}  // namespace rowk
 
 }  // namespace spinlat

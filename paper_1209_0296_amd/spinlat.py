@@ -79,6 +79,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1209_0296_amd.build` (hipcc, gfx950)")
+    # torch's HIP runtime must be the one in the process before the library
+    # binds to libamdhip64 (same soname): device buffers and streams come from
+    # torch, and a second runtime would not see the device.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     P, H = ctypes.POINTER(CParams), ctypes.c_void_p
     sz = ctypes.c_size_t

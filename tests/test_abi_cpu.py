@@ -103,11 +103,12 @@ def test_status_strings():
         assert S.lib().sl_status_str(code).decode() == name
 
 
-def test_batch_rejects_unbatchable_shapes():
+def test_batch_shapes():
     cfg = S.batch_config(max_jobs=4, record_capacity=8)
     with pytest.raises(S.SpinlatError) as e:
-        S.batch_job_bytes(S.Params(L=2056), cfg)  # 257-word colour rows
+        S.batch_job_bytes(S.Params(L=12), cfg)  # 12 % 8 != 0
     assert e.value.status == 2
-    with pytest.raises(S.SpinlatError) as e:
-        S.batch_job_bytes(S.Params(L=64, T=0.05), cfg)  # zero thresholds
-    assert e.value.status == 2
+    # rows wider than one wave and zero thresholds go to the window kernels
+    for p in (S.Params(L=2056), S.Params(L=936), S.Params(L=64, T=0.05)):
+        n = S.batch_job_bytes(p, cfg)
+        assert n >= p.nsites

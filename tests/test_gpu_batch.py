@@ -22,6 +22,9 @@ def _mixed_jobs():
         S.Params(dim=3, L=64, T=4.0, J=0.9, seed=8),
         S.Params(model=S.NORTH_EAST, L=72, c=0.2, seed=9),
         S.Params(model=S.NORTH_EAST, L=128, c=0.1, seed=10),
+        S.Params(L=936, T=2.3, seed=11),                   # 117-word rows: window kernel
+        S.Params(L=64, T=0.05, seed=12),                   # zero thresholds: window kernel
+        S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),
     ]
     return jobs
 
@@ -34,7 +37,7 @@ def _check_job(batch, jid, sp, recs, nsweeps):
 
 def test_mixed_batch_matches_each_job_alone():
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=64 << 20, max_jobs=16, record_capacity=64)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=64)
     ids = [b.add(p, sweeps=12) for p in jobs]
     assert all(i is not None for i in ids)
     recs = {i: [S.records_to_array(b.measure(i))] for i in ids}
@@ -117,7 +120,7 @@ def test_batch_equals_standalone_lattice():
 def test_drain_collects_every_job():
     """sl_batch_drain (one fold launch, one copy) gives each job's records."""
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=64 << 20, max_jobs=16, record_capacity=8)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=8)
     ids = [b.add(p, sweeps=10 + k) for k, p in enumerate(jobs)]
     recs = {i: [] for i in ids}
     while True:

@@ -55,3 +55,26 @@ def random_lattice(shape, two_s: int = 1, seed: int = 0, model: int = 0,
     if two_s == 1:
         return (2 * rng.integers(0, 2, size=shape, dtype=np.int8) - 1).astype(np.int8)
     return rng.integers(-1, 2, size=shape, dtype=np.int8)
+
+
+def served_requests(n: int = 4096, rate: float = 1000.0, seed: int = 5,
+                    sweeps=(1000, 10000)):
+    """Poisson stream of independent Ising jobs shaped like the served batch:
+    2D L log-uniform in [32, 1024] or 3D L log-uniform in [16, 128] (rounded to
+    a multiple of 8), spin-1/2 or spin-1, T uniform in [0.8, 1.2] x T_c of the
+    model, a sweep count uniform in `sweeps`, and a distinct seed per job.
+    Returns a list of dicts {id, arrival (s), dim, L, two_s, T, seed, sweeps}."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        dim = 2 if rng.random() < 0.5 else 3
+        lo, hi = (32, 1024) if dim == 2 else (16, 128)
+        L = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        L = int(min(hi, max(lo, 8 * round(L / 8))))
+        two_s = 1 if rng.random() < 0.5 else 2
+        T = float(rng.uniform(0.8, 1.2) * TC_ESTIMATE[(dim, two_s)])
+        out.append(dict(id=i, arrival=t, dim=dim, L=L, two_s=two_s, T=T, seed=100000 + i,
+                        sweeps=int(rng.integers(sweeps[0], sweeps[1] + 1))))
+    return out
