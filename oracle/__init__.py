@@ -29,6 +29,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ISING = 0
 NORTH_EAST = 1
+NE_TILES = 2  # North-East model, the paper's random sub-lattice algorithm
 INIT_COLD = 0
 INIT_RANDOM = 1
 RECORD_WORDS = 5  # t, bond_sum, mag, accepted, unflipped
@@ -53,6 +54,7 @@ class _Params(ctypes.Structure):
         ("two_s", ctypes.c_int32), ("init", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("J", ctypes.c_double), ("h", ctypes.c_double), ("T", ctypes.c_double),
         ("c", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("tile", ctypes.c_int32), ("lambda_", ctypes.c_int32),
     ]
 
 
@@ -91,6 +93,8 @@ def lib():
         L.or_run.argtypes = [P, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                              ctypes.c_void_p, ctypes.c_int]
         L.or_run.restype = ctypes.c_int
+        L.or_ne_tiles_launch.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+        L.or_ne_tiles_launch.restype = ctypes.c_int64
         L.or_threshold_table.argtypes = [P, ctypes.c_void_p, ctypes.c_int64]
         L.or_threshold_table.restype = ctypes.c_int64
         _lib = L
@@ -100,7 +104,9 @@ def lib():
 @dataclass
 class Params:
     """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1,
-    2D or 3D) or the North-East model (up-density c, 2D)."""
+    2D or 3D) or the North-East model (up-density c, 2D), the latter either by
+    checkerboard half-sweeps (NORTH_EAST) or by the paper's random sub-lattice
+    algorithm (NE_TILES: side ``tile``, ``lam`` sites per iteration)."""
     model: int = ISING
     dim: int = 2
     L: int = 64
@@ -111,10 +117,12 @@ class Params:
     T: float = 2.269
     c: float = 0.1
     seed: int = 1
+    tile: int = 32   # NE_TILES: side of the sub-lattices
+    lam: int = 16    # NE_TILES: sites updated together per iteration
 
     def c_struct(self) -> _Params:
         return _Params(self.model, self.dim, self.L, self.two_s, self.init, 0,
-                       self.J, self.h, self.T, self.c, self.seed)
+                       self.J, self.h, self.T, self.c, self.seed, self.tile, self.lam)
 
     @property
     def nsites(self) -> int:
@@ -191,9 +199,22 @@ def run(p: Params, s: np.ndarray, t0: int, nsweeps: int, records: bool = True,
     assert s.dtype == np.int8 and s.flags.c_contiguous and s.size == p.nsites
     rec = np.zeros((nsweeps, RECORD_WORDS), dtype=np.int64) if records else None
     ps = p.c_struct()
-    lib().or_run(ctypes.byref(ps), s.ctypes.data, t0, nsweeps,
-                 rec.ctypes.data if rec is not None else None, nthreads)
+    rc = lib().or_run(ctypes.byref(ps), s.ctypes.data, t0, nsweeps,
+                      rec.ctypes.data if rec is not None else None, nthreads)
+    if rc != 0:
+        raise ValueError("invalid parameters for the oracle run")
     return rec
+
+
+def ne_tiles_launch(p: Params, src: np.ndarray, launch: int):
+    """One launch of the paper's NE algorithm: returns (new lattice, accepted)."""
+    dst = np.empty_like(src)
+    ps = p.c_struct()
+    assert src.dtype == np.int8 and src.flags.c_contiguous and src.size == p.nsites
+    acc = lib().or_ne_tiles_launch(ctypes.byref(ps), src.ctypes.data, dst.ctypes.data, launch)
+    if acc < 0:
+        raise ValueError("invalid sub-lattice parameters")
+    return dst, int(acc)
 
 
 def initial_record(p: Params, s: np.ndarray, t: int = 0) -> np.ndarray:

@@ -21,6 +21,9 @@
  *     n in {0,1}; a site may change only when its north and east neighbours
  *     are both up (n = 1); then the Metropolis rule applies with equilibrium
  *     up-density c (excitation energy 1, c = 1/(1+e^{1/T})).
+ *   - Sec. 3.2, the NE algorithm with random sub-lattices: square sub-lattices,
+ *     lambda random sites per iteration, two launches per sweep
+ *     (or_ne_tiles_launch below, with its readings).
  *
  * Readings of points the paper leaves open (all documented in the design
  * notes of the repository):
@@ -190,7 +193,7 @@ void or_init(const or_params* p, int8_t* s)
                 uint64_t k = (uint64_t)i >> 1;
                 uint32_t u = or_rand(p->seed, OR_TAG_INIT, 0, colour, k, 1, 0);
                 int8_t v;
-                if (p->model == OR_NORTH_EAST) {
+                if (p->model != OR_ISING) {
                     v = (int8_t)(((uint64_t)u < bern_thr) ? 1 : 0);
                 } else if (p->init == OR_INIT_COLD) {
                     v = 1;
@@ -282,6 +285,7 @@ static int64_t half_sweep_ne(const or_params* p, int8_t* s, uint32_t t, uint32_t
 int64_t or_half_sweep(const or_params* p, int8_t* s, uint32_t t, uint32_t colour)
 {
     if (p->model == OR_NORTH_EAST) return half_sweep_ne(p, s, t, colour);
+    if (p->model != OR_ISING) return -1;     /* no colour half-sweeps */
     return half_sweep_ising(p, s, t, colour);
 }
 
@@ -300,7 +304,7 @@ void or_recount(const or_params* p, const int8_t* s, int64_t out[3])
             for (int x = 0; x < L; ++x) {
                 int64_t i = idx3(L, x, y, z);
                 int v, vx, vy, vz = 0;
-                if (p->model == OR_NORTH_EAST) {
+                if (p->model != OR_ISING) {
                     v = s[i] & 1;
                     vx = s[idx3(L, wrap(x + 1, L), y, z)] & 1;
                     vy = s[idx3(L, x, wrap(y + 1, L), z)] & 1;
@@ -316,14 +320,93 @@ void or_recount(const or_params* p, const int8_t* s, int64_t out[3])
             }
     out[0] = bond;
     out[1] = mag;
-    out[2] = (p->model == OR_NORTH_EAST) ? unflipped : -1;
+    out[2] = (p->model != OR_ISING) ? unflipped : -1;
 }
 
 void or_reset_persistence(const or_params* p, int8_t* s)
 {
-    if (p->model != OR_NORTH_EAST) return;
+    if (p->model == OR_ISING) return;
     int64_t N = or_nsites(p);
     for (int64_t i = 0; i < N; ++i) s[i] = (int8_t)(s[i] & 1);
+}
+
+/* ---------------------------------------------------------------------- */
+/* The paper's own North-East algorithm (Sec. 3.2, Alg. NE): the lattice is cut
+ * into Q square sub-lattices of P = B*B sites.  In each launch every
+ * sub-lattice is processed once: q = P/(2 lambda) times, lambda sites of the
+ * sub-lattice are drawn at random and updated together, then the sub-lattice
+ * is synchronised.  Two launches make one sweep (q * lambda * 2 = P attempts
+ * per sub-lattice).
+ *
+ * Readings: a neighbour that belongs to another sub-lattice (the north row
+ * and east column copied with the sub-lattice) is read as it was when the
+ * launch started -- the launch reads `src` and writes `dst` -- so the order in
+ * which sub-lattices are processed (the paper's random assignment of
+ * sub-lattices to blocks) cannot change the result; a neighbour inside the
+ * same sub-lattice (including the periodic wrap when B = L, Q = 1) is read
+ * live.  The lambda updates of one iteration all read the sub-lattice as it
+ * was at the start of the iteration, and an accepted move sets n to 1-n (the
+ * same byte for every thread that drew the site), so sites drawn twice need no
+ * tie-break.  With Q = lambda = 1 this is the serial random-site Metropolis
+ * algorithm.  Random numbers: attempt
+ * a = j*lambda + l (thread l of iteration j) on sub-lattice tau in launch
+ * `launch` uses words 2*(a mod 2) and 2*(a mod 2)+1 of
+ * Philox4x32-10(key = seed, ctr = (tau, a/2, launch, 2)): the first picks the
+ * site floor(word * P / 2^32) (row-major in the sub-lattice), the second
+ * decides acceptance.  Sub-lattices are numbered row-major, tau = (y0/B) *
+ * (L/B) + x0/B.  `accepted` counts, per iteration, the sites whose value
+ * changed.  Sweep t uses launches 2t and 2t+1. */
+
+int64_t or_ne_tiles_launch(const or_params* p, const int8_t* src, int8_t* dst, uint32_t launch)
+{
+    const int L = p->L, B = p->tile, lam = p->lambda;
+    if (p->dim != 2 || B < 2 || lam < 1 || L % B != 0 || (B * B) % (2 * lam) != 0) return -1;
+    const int P = B * B, tiles_x = L / B, q = P / (2 * lam);
+    const uint64_t thr_up = or_threshold_from_prob(p->c / (1.0 - p->c));
+    const uint64_t thr_down = or_threshold_from_prob((1.0 - p->c) / p->c);
+    memcpy(dst, src, (size_t)L * L);
+    int64_t accepted = 0;
+#pragma omp parallel for schedule(static) reduction(+ : accepted)
+    for (int tau = 0; tau < tiles_x * tiles_x; ++tau) {
+        const int x0 = (tau % tiles_x) * B, y0 = (tau / tiles_x) * B;
+        int8_t* tile = (int8_t*)malloc((size_t)P);
+        int8_t* next = (int8_t*)malloc((size_t)P);
+        for (int r = 0; r < B; ++r)
+            for (int cc = 0; cc < B; ++cc) tile[r * B + cc] = src[idx3(L, x0 + cc, y0 + r, 0)];
+        for (int j = 0; j < q; ++j) {
+            memcpy(next, tile, (size_t)P);
+            for (int l = 0; l < lam; ++l) {
+                const uint32_t a = (uint32_t)(j * lam + l);
+                uint32_t ctr[4] = {(uint32_t)tau, a / 2, launch, OR_TAG_NE_TILES};
+                uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+                uint32_t w[4];
+                or_philox4x32_10(ctr, key, w);
+                const uint32_t site_word = w[(a % 2) * 2];
+                const uint32_t acc_word = w[(a % 2) * 2 + 1];
+                const int s = (int)(((uint64_t)site_word * (uint64_t)P) >> 32);
+                const int r = s / B, cc = s % B;
+                const int n = tile[s] & 1;
+                int north, east;
+                if (r > 0) north = tile[(r - 1) * B + cc] & 1;
+                else if (tiles_x == 1) north = tile[(B - 1) * B + cc] & 1;
+                else north = src[idx3(L, x0 + cc, wrap(y0 - 1, L), 0)] & 1;
+                if (cc < B - 1) east = tile[r * B + cc + 1] & 1;
+                else if (tiles_x == 1) east = tile[r * B] & 1;
+                else east = src[idx3(L, wrap(x0 + B, L), y0 + r, 0)] & 1;
+                if (!(north && east)) continue;
+                const uint64_t thr = n ? thr_down : thr_up;
+                if ((uint64_t)acc_word < thr) next[s] = (int8_t)((n ^ 1) | 2);
+            }
+            for (int i = 0; i < P; ++i)
+                if (next[i] != tile[i]) accepted += 1;
+            memcpy(tile, next, (size_t)P);
+        }
+        for (int r = 0; r < B; ++r)
+            for (int cc = 0; cc < B; ++cc) dst[idx3(L, x0 + cc, y0 + r, 0)] = tile[r * B + cc];
+        free(tile);
+        free(next);
+    }
+    return accepted;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -340,11 +423,26 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
 #else
     (void)nthreads;
 #endif
+    int8_t* tmp = NULL;
+    if (p->model == OR_NE_TILES) {
+        tmp = (int8_t*)malloc((size_t)p->L * p->L);
+        if (!tmp) return -1;
+    }
     for (uint32_t n = 0; n < nsweeps; ++n) {
         uint32_t t = t0 + n;
         int64_t acc = 0;
-        acc += or_half_sweep(p, s, t, 0);
-        acc += or_half_sweep(p, s, t, 1);
+        if (p->model == OR_NE_TILES) {
+            const int64_t a0 = or_ne_tiles_launch(p, s, tmp, 2 * t);
+            const int64_t a1 = a0 < 0 ? -1 : or_ne_tiles_launch(p, tmp, s, 2 * t + 1);
+            if (a1 < 0) {
+                free(tmp);
+                return -1;
+            }
+            acc = a0 + a1;
+        } else {
+            acc += or_half_sweep(p, s, t, 0);
+            acc += or_half_sweep(p, s, t, 1);
+        }
         if (records) {
             int64_t obs[3];
             or_recount(p, s, obs);
@@ -356,6 +454,7 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
             r[4] = obs[2];
         }
     }
+    free(tmp);
     return 0;
 }
 
@@ -367,7 +466,7 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
 
 int64_t or_threshold_table(const or_params* p, uint64_t* out, int64_t cap)
 {
-    if (p->model == OR_NORTH_EAST) {
+    if (p->model != OR_ISING) {
         if (cap < 2) return -1;
         out[0] = or_threshold_from_prob(p->c / (1.0 - p->c));
         out[1] = or_threshold_from_prob((1.0 - p->c) / p->c);

@@ -15,14 +15,16 @@ extern "C" {
 #define OR_ABI 1
 #define OR_ISING 0
 #define OR_NORTH_EAST 1
+#define OR_NE_TILES 2   /* North-East model, paper's random sub-lattice algorithm */
 #define OR_INIT_COLD 0
 #define OR_INIT_RANDOM 1
 #define OR_TAG_SWEEP 0u
 #define OR_TAG_INIT 1u
+#define OR_TAG_NE_TILES 2u
 #define OR_RECORD_WORDS 5
 
 typedef struct {
-    int32_t model;   /* OR_ISING or OR_NORTH_EAST */
+    int32_t model;   /* OR_ISING, OR_NORTH_EAST or OR_NE_TILES */
     int32_t dim;     /* 2 or 3 (NE: 2) */
     int32_t L;       /* even */
     int32_t two_s;   /* 1: s in {-1,+1}; 2: s in {-1,0,+1} */
@@ -31,6 +33,8 @@ typedef struct {
     double J, h, T;  /* Ising */
     double c;        /* NE up-density, 0 < c < 1 */
     uint64_t seed;
+    int32_t tile;    /* OR_NE_TILES: side B of the square sub-lattices */
+    int32_t lambda;  /* OR_NE_TILES: sites updated together per iteration */
 } or_params;
 
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -47,6 +51,7 @@ void or_reset_persistence(const or_params* p, int8_t* s);
 int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
            int64_t* records, int nthreads);
 int64_t or_threshold_table(const or_params* p, uint64_t* out, int64_t cap);
+int64_t or_ne_tiles_launch(const or_params* p, const int8_t* src, int8_t* dst, uint32_t launch);
 int or_abi(void);
 
 #ifdef __cplusplus
