@@ -319,6 +319,7 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
     hj->acc = ring_of(b, j);
     hj->key0 = (uint32_t)J.params.seed;
     hj->key1 = (uint32_t)(J.params.seed >> 32);
+    hj->cls = batch_class(J.kind, J.params.dim, J.geom.D);
     std::memcpy(hj->rg_words, J.geom.bytes, sizeof(hj->rg_words));
     std::memcpy(hj->table, J.table, J.table_n * sizeof(uint64_t));
     hipError_t e = hipMemcpyAsync(d_jobs(b) + j, hj, sizeof(BatchJob), hipMemcpyHostToDevice, b->stream);
@@ -410,15 +411,14 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
         e = hipMemcpyAsync(d_wgs(b), b->h_wgs, nwg * sizeof(BatchWG), hipMemcpyHostToDevice, b->stream);
     // the staging buffers are rewritten by the next call: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    // one launch per colour for every job (the work list is grouped by
+    // variant), then the counter advance
     for (uint64_t s = 0; s < n_eff && e == hipSuccess; ++s) {
         for (uint32_t colour = 0; colour < 2 && e == hipSuccess; ++colour)
-            for (const Cls& c : classes) {
-                e = launch_batch_class(c.kind, c.dim, c.D, d_jobs(b), d_dyn(b), d_wgs(b) + c.begin, c.count,
-                                       colour, b->stream);
-                if (e != hipSuccess) break;
-            }
+            e = launch_batch_all(d_jobs(b), d_dyn(b), d_wgs(b), (uint32_t)nwg, colour, b->stream);
         if (e == hipSuccess) e = launch_batch_advance(d_dyn(b), top, b->stream);
     }
+    (void)classes;
     if (e != hipSuccess) return hip_fail(e, "batch sweep");
     for (uint32_t j = 0; j < top; ++j) {
         JobHost& J = b->jobs[j];

@@ -15,6 +15,8 @@ struct BatchJob {
     uint8_t* col[2];           // colour arrays
     unsigned long long* acc;   // record ring [capacity][kSub][kQ]
     uint32_t key0, key1;       // Philox key = seed
+    uint32_t cls;              // kernel variant: batch_class(kind, dim, D)
+    uint32_t pad;
     uint32_t rg_words[16];     // whole-row geometry of the job (RowGeom)
     uint64_t table[kTableMax]; // threshold table (NE: up, down)
 };
@@ -45,6 +47,17 @@ struct RowGeomHost {
 bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out);
 hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,
                               const BatchWG* wgs, uint32_t nwg, uint32_t colour, hipStream_t s);
+
+// Variant index of a job for the one-launch kernel: kind, dimension and D.
+inline uint32_t batch_class(int kind, int dim, int D)
+{
+    const uint32_t d = D == 4 ? 0u : D == 2 ? 1u : D == 1 ? 2u : 3u;
+    return (uint32_t)kind * 8u + (uint32_t)(dim - 2) * 4u + d;
+}
+
+// All jobs of a half-sweep in one launch (work list sorted by variant).
+hipError_t launch_batch_all(const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
+                            uint32_t colour, hipStream_t s);
 hipError_t launch_batch_advance(uint32_t* dyn, uint32_t njobs, hipStream_t s);
 hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* out, hipStream_t s);
 

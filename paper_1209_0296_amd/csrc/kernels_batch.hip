@@ -24,13 +24,10 @@ using namespace rowk;
 namespace {
 
 template <int KIND, int DIM, int D>
-__global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__ jobs,
-                                                    const uint32_t* __restrict__ dyn,
-                                                    const BatchWG* __restrict__ wgs, uint32_t colour)
+__device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ jobs, const uint32_t* __restrict__ dyn,
+                                                const BatchWG w, uint32_t colour, RowLuts& lut,
+                                                uint32_t (&xch)[2][16][2])
 {
-    __shared__ RowLuts lut;
-    __shared__ uint32_t xch[2][16][2];
-    const BatchWG w = wgs[blockIdx.x];
     const uint32_t* dj = dyn + kDynWords * w.job;
     const uint32_t remaining = dj[2];
     if (remaining == 0) return;  // whole workgroup: this job has no sweep left in this call
@@ -62,12 +59,10 @@ __global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__
 // Jobs whose colour row does not fit one wave (or whose spin-1/2 table has a
 // zero threshold): 64-lane column windows with edge loads (any L % 8 == 0).
 template <int KIND, int DIM>
-__global__ void __launch_bounds__(256) k_batch_window(const BatchJob* __restrict__ jobs,
-                                                      const uint32_t* __restrict__ dyn,
-                                                      const BatchWG* __restrict__ wgs, uint32_t colour)
+__device__ __forceinline__ void batch_window_body(const BatchJob* __restrict__ jobs,
+                                                  const uint32_t* __restrict__ dyn, const BatchWG w,
+                                                  uint32_t colour, streamk::Luts& lut)
 {
-    __shared__ streamk::Luts lut;
-    const BatchWG w = wgs[blockIdx.x];
     const uint32_t* dj = dyn + kDynWords * w.job;
     if (dj[2] == 0) return;  // whole workgroup: no sweep left for this job
     const BatchJob& J = jobs[w.job];
@@ -88,6 +83,63 @@ __global__ void __launch_bounds__(256) k_batch_window(const BatchJob* __restrict
     const uint32_t item = w.item_base + (threadIdx.x >> 6) * sg.G + lane / sg.W;
     streamk::stream_half_item<KIND, DIM>(a, sg, item, lut, thr_up, thr_down, o);
     block_accumulate(o.bond, o.mag, o.acc, o.unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
+}
+
+template <int KIND, int DIM, int D>
+__global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ dyn,
+                                                    const BatchWG* __restrict__ wgs, uint32_t colour)
+{
+    __shared__ RowLuts lut;
+    __shared__ uint32_t xch[2][16][2];
+    batch_half_body<KIND, DIM, D>(jobs, dyn, wgs[blockIdx.x], colour, lut, xch);
+}
+
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(256) k_batch_window(const BatchJob* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ dyn,
+                                                      const BatchWG* __restrict__ wgs, uint32_t colour)
+{
+    __shared__ streamk::Luts lut;
+    batch_window_body<KIND, DIM>(jobs, dyn, wgs[blockIdx.x], colour, lut);
+}
+
+// Every job of a half-sweep in one launch: each workgroup runs the variant of
+// its job (the work list is sorted by variant, so neighbouring workgroups run
+// the same code).
+union BatchLds {
+    RowLuts row;
+    streamk::Luts win;
+};
+
+template <int KIND, int DIM>
+__device__ __forceinline__ void dispatch_d(uint32_t d, const BatchJob* jobs, const uint32_t* dyn, const BatchWG w,
+                                           uint32_t colour, BatchLds& lds, uint32_t (&xch)[2][16][2])
+{
+    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, lds.row, xch);
+    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, lds.row, xch);
+    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, lds.row, xch);
+    else batch_window_body<KIND, DIM>(jobs, dyn, w, colour, lds.win);
+}
+
+__global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ jobs,
+                                                   const uint32_t* __restrict__ dyn,
+                                                   const BatchWG* __restrict__ wgs, uint32_t colour)
+{
+    __shared__ BatchLds lds;
+    __shared__ uint32_t xch[2][16][2];
+    const BatchWG w = wgs[blockIdx.x];
+    const uint32_t cls = jobs[w.job].cls;
+    const uint32_t kind = cls >> 3, dim3d = (cls >> 2) & 1u, d = cls & 3u;
+    if (kind == KIND_ISING_HALF) {
+        if (dim3d) dispatch_d<KIND_ISING_HALF, 3>(d, jobs, dyn, w, colour, lds, xch);
+        else dispatch_d<KIND_ISING_HALF, 2>(d, jobs, dyn, w, colour, lds, xch);
+    } else if (kind == KIND_ISING_ONE) {
+        if (dim3d) dispatch_d<KIND_ISING_ONE, 3>(d, jobs, dyn, w, colour, lds, xch);
+        else dispatch_d<KIND_ISING_ONE, 2>(d, jobs, dyn, w, colour, lds, xch);
+    } else {
+        dispatch_d<KIND_NE, 2>(d, jobs, dyn, w, colour, lds, xch);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_batch_advance(uint32_t* dyn, uint32_t njobs)
@@ -186,6 +238,14 @@ hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* o
 {
     if (nentries == 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_fold, dim3(nentries), dim3(256), 0, s, tab, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_all(const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
+                            uint32_t colour, hipStream_t s)
+{
+    if (nwg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_all, dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
     return hipGetLastError();
 }
 
