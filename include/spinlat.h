@@ -14,7 +14,16 @@
  *     integer compare of a 32-bit Philox4x32-10 word against a threshold
  *     table computed on the host in double precision;
  *   - one sweep = colour 0 (sites with (x+y[+z]) even) then colour 1
- *     (Alg. I steps 5-7, Fig. 3: two non-interacting sub-lattices).
+ *     (Alg. I steps 5-7, Fig. 3: two non-interacting sub-lattices);
+ *   - the North-East model also by the paper's random sub-lattice algorithm
+ *     (Sec. 3.2, model SL_NE_SUBLATTICE): square sub-lattices of B x B sites,
+ *     each launch makes q = B^2 / (2 lambda) iterations per sub-lattice in
+ *     which lambda random sites are updated together, two launches per sweep.
+ *     Neighbours in another sub-lattice are read as at the start of the launch,
+ *     neighbours in the same sub-lattice as at the start of the iteration; an
+ *     accepted move sets n to 1-n, so a site drawn twice in one iteration
+ *     flips once.  With B = L and lambda = 1 (not offered by the kernels) this
+ *     would be the serial random-site algorithm.
  *
  * Random-number contract (result is a pure function of seed, sweep and site,
  * so any launch schedule gives the same lattice bit for bit):
@@ -27,6 +36,11 @@
  *   word j=1 picks the proposal (lower of the two other values iff < 2^31).
  *   NE: word decides up-flips (thr = floor(min(1, c/(1-c)) 2^32)) and
  *   down-flips (floor(min(1, (1-c)/c) 2^32)).
+ *   NE sub-lattices: attempt a = j*lambda + l (thread l, iteration j) on
+ *   sub-lattice tau = (y0/B)*(L/B) + x0/B in launch m (m = 2t, then 2t+1) uses
+ *   words 2(a mod 2) and 2(a mod 2)+1 of Philox4x32-10(key = seed,
+ *   ctr = (tau, a/2, m, 2)): the first picks the site floor(word B^2 / 2^32)
+ *   (row-major in the sub-lattice), the second is compared with the threshold.
  *   Initial state: word(seed, 1, 0, colour, k, 1, 0): spin-1/2 +1 iff
  *   < 2^31; spin-1 floor(3 word / 2^32) - 1; NE up iff < floor(c 2^32).
  *   Threshold: thr(dE) = 2^32 if dE <= 0, else floor(exp(-dE/T) 2^32), with
@@ -35,7 +49,8 @@
  *
  * Records: record r_0 describes the state at creation; r_{i+1} the state after
  * sweep t0+i: {t, bond_sum = sum_i sum_{d<dim} s_i s_{i+e_d}, mag = sum_i s_i
- * (NE: sum_i n_i, bond_sum over n), accepted = moves accepted in that sweep,
+ * (NE: sum_i n_i, bond_sum over n), accepted = moves accepted in that sweep
+ * (NE sub-lattices: per iteration, the number of sites that changed),
  * unflipped = NE sites not flipped since the persistence origin (-1 for
  * Ising)}.  Energy: Ising E = -J bond_sum - h mag.
  *
@@ -56,7 +71,7 @@
 extern "C" {
 #endif
 
-#define SL_ABI_VERSION 1u
+#define SL_ABI_VERSION 2u
 
 typedef struct sl_lattice sl_lattice; /* opaque, owned by the library */
 
@@ -67,10 +82,14 @@ typedef enum sl_status {
     SL_E_BUFFER = 3,      /* caller buffer too small, misaligned or NULL */
     SL_E_HIP = 4,         /* a HIP runtime call failed (message has its text) */
     SL_E_STATE = 5,       /* call not allowed now (record ring full, ...) */
-    SL_E_OVERFLOW = 6     /* sweep index would reach 2^32 */
+    SL_E_OVERFLOW = 6     /* sweep index would reach 2^32 (NE sub-lattices: 2^31) */
 } sl_status;
 
-typedef enum sl_model { SL_ISING = 0, SL_NORTH_EAST = 1 } sl_model;
+typedef enum sl_model {
+    SL_ISING = 0,
+    SL_NORTH_EAST = 1,    /* NE model, checkerboard half-sweeps */
+    SL_NE_SUBLATTICE = 2  /* NE model, random sub-lattice algorithm (Sec. 3.2) */
+} sl_model;
 
 typedef enum sl_init {
     SL_INIT_COLD = 0,   /* Ising: every spin +1 */
@@ -92,6 +111,10 @@ typedef struct sl_params {
     uint64_t record_capacity; /* records held on the device between sl_measure calls, >= 1 */
     const int8_t* init_spins; /* SL_INIT_BUFFER: device pointer to L^dim bytes in natural
                                  row-major order [z][y][x] (Ising: s; NE: n | flag<<1) */
+    int32_t ne_side;          /* SL_NE_SUBLATTICE: sub-lattice side B in {8,16,32,64},
+                                 L % B == 0 (ignored by the other models) */
+    int32_t ne_lambda;        /* SL_NE_SUBLATTICE: sites updated together, a power of two
+                                 in [2, 128] with 2 lambda <= B^2 (ignored otherwise) */
 } sl_params;
 
 typedef struct sl_record {
@@ -142,7 +165,8 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
 /* Choose the launch schedule for later sweeps (validated; SL_E_UNSUPPORTED if
  * the schedule does not fit the shape: HALF/FUSED need the colour row to split
  * into row groups of <= 64 lanes or a multiple of 64 lanes up to 1024, and for
- * spin-1/2 every threshold >= 1; the window modes take any shape). */
+ * spin-1/2 every threshold >= 1; the window modes take any shape).  NE
+ * sub-lattice lattices have one schedule and accept only SL_MODE_AUTO. */
 sl_status sl_set_launch(sl_lattice* lat, const sl_launch* launch);
 sl_status sl_get_launch(const sl_lattice* lat, sl_launch* launch);
 
@@ -162,8 +186,8 @@ sl_status sl_status_counts(const sl_lattice* lat, uint64_t* pending, uint64_t* n
  * row-major order, NE bytes include the flag bit).  Asynchronous. */
 sl_status sl_copy_spins(sl_lattice* lat, int8_t* device_out, size_t n);
 
-/* NE: clear every "has flipped" flag; the persistence origin becomes the
- * current sweep.  Asynchronous.  SL_E_STATE for Ising lattices. */
+/* NE (either algorithm): clear every "has flipped" flag; the persistence
+ * origin becomes the current sweep.  Asynchronous.  SL_E_STATE for Ising. */
 sl_status sl_reset_persistence(sl_lattice* lat);
 
 /* Release the handle (never frees the borrowed buffer).  Synchronises. */
@@ -188,7 +212,8 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
  * lists at the start of it and places every job's lattice and record ring in
  * the rest.  A job is admitted only if its footprint (sl_batch_job_bytes) fits
  * in the free arena space; removing a job returns its space.
- * Batched jobs need L % 8 == 0.  Jobs whose colour row splits into row groups
+ * Batched jobs need L % 8 == 0 and a checkerboard model (SL_ISING or
+ * SL_NORTH_EAST).  Jobs whose colour row splits into row groups
  * of at most 64 lanes run the whole-row kernels, the others the column-window
  * kernels (also spin-1/2 jobs with a zero threshold).
  * ------------------------------------------------------------------------- */

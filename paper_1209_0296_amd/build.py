@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspinlat.so")
 SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "kernels_row.hip", "kernels_batch.hip",
-           "runtime.cpp", "batch.cpp"]
+           "kernels_ne_sub.hip", "runtime.cpp", "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

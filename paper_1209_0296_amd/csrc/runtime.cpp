@@ -43,7 +43,7 @@ sl_status hip_fail(hipError_t e, const char* what)
 
 int kind_of(const sl_params* p)
 {
-    if (p->model == SL_NORTH_EAST) return KIND_NE;
+    if (p->model != SL_ISING) return KIND_NE;
     return p->two_s == 1 ? KIND_ISING_HALF : KIND_ISING_ONE;
 }
 
@@ -52,7 +52,7 @@ sl_status validate(const sl_params* p)
     if (!p) return fail(SL_E_INVALID, "params is NULL");
     if (p->abi_version != SL_ABI_VERSION)
         return fail(SL_E_INVALID, "abi_version %u != %u", p->abi_version, SL_ABI_VERSION);
-    if (p->model != SL_ISING && p->model != SL_NORTH_EAST)
+    if (p->model != SL_ISING && p->model != SL_NORTH_EAST && p->model != SL_NE_SUBLATTICE)
         return fail(SL_E_INVALID, "unknown model %d", p->model);
     if (p->dim != 2 && p->dim != 3) return fail(SL_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
     if (p->L < 2 || (p->L & 1))
@@ -75,6 +75,18 @@ sl_status validate(const sl_params* p)
             return fail(SL_E_INVALID, "c must lie in (0, 1) (got %g)", p->c);
         if (p->init == SL_INIT_COLD)
             return fail(SL_E_INVALID, "NE lattices start from Bernoulli(c) or a buffer");
+    }
+    if (p->model == SL_NE_SUBLATTICE) {
+        const int B = p->ne_side, lam = p->ne_lambda;
+        if (B < 2 || lam < 1 || p->L % B != 0 || (B * B) % (2 * lam) != 0)
+            return fail(SL_E_INVALID, "sub-lattices need L %% B == 0 and B^2 %% (2 lambda) == 0 "
+                                      "(L %d, B %d, lambda %d)", p->L, B, lam);
+        if (!ne_sub_supported((uint32_t)p->L, B, lam))
+            return fail(SL_E_UNSUPPORTED, "the sub-lattice kernels take B in {8,16,32,64} and "
+                                          "lambda a power of two in [2,128] (B %d, lambda %d)",
+                        B, lam);
+        if (p->t0 >= (1ull << 31))
+            return fail(SL_E_OVERFLOW, "t0 must be < 2^31 (two launch indices per sweep)");
     }
     if (p->t0 >= (1ull << 32)) return fail(SL_E_OVERFLOW, "t0 must be < 2^32");
     if (p->record_capacity < 1 || p->record_capacity > (1ull << 32))
@@ -121,7 +133,7 @@ uint64_t thr_from_energy(double dE, double T)
 
 size_t build_table(const sl_params* p, uint64_t* out)
 {
-    if (p->model == SL_NORTH_EAST) {
+    if (p->model != SL_ISING) {
         out[0] = thr_from_prob(p->c / (1.0 - p->c));  // up-flip: energy +1
         out[1] = thr_from_prob((1.0 - p->c) / p->c);  // down-flip
         return 2;
@@ -237,6 +249,11 @@ sl_launch auto_launch(const sl_lattice* h)
 
 sl_status check_launch(const sl_lattice* h, sl_launch* l)
 {
+    if (h->params.model == SL_NE_SUBLATTICE) {
+        if (l->mode != SL_MODE_AUTO)
+            return fail(SL_E_UNSUPPORTED, "NE sub-lattice lattices have one schedule (SL_MODE_AUTO)");
+        return SL_OK;
+    }
     const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
                     0u, h->lay.nh};
     switch (l->mode) {
@@ -282,6 +299,59 @@ sl_status enqueue_observe(sl_lattice* h, uint64_t slot)
         hipError_t e = launch_simple_half(a, h->kind, h->stream);
         if (e != hipSuccess) return hip_fail(e, "observe kernel");
     }
+    return SL_OK;
+}
+
+// Paper Sec. 3.2, NE algorithm with random sub-lattices: per sweep, launch
+// 2t reads the current copy and writes the other, launch 2t+1 reads that and
+// writes the current copy back; the record of the sweep is then observed
+// from the current copy (both colours, no update) into the same slot the two
+// launches added their accepted counts to.
+sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
+{
+    const int B = h->params.ne_side, lam = h->params.ne_lambda;
+    const uint32_t L = (uint32_t)h->params.L;
+    NeSubArgs na{};
+    na.L = L;
+    na.Lh = L / 2;
+    na.tiles_x = L / (uint32_t)B;
+    na.ntiles = na.tiles_x * na.tiles_x;
+    na.key0 = (uint32_t)h->params.seed;
+    na.key1 = (uint32_t)(h->params.seed >> 32);
+    na.wrap = na.tiles_x == 1 ? 1u : 0u;
+    na.thr_up = h->table[0];
+    na.thr_down = h->table[1];
+    uint8_t* cur[2] = {h->base + h->lay.off_col[h->cur][0], h->base + h->lay.off_col[h->cur][1]};
+    uint8_t* oth[2] = {h->base + h->lay.off_col[h->cur ^ 1][0],
+                       h->base + h->lay.off_col[h->cur ^ 1][1]};
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t t = h->next_t + i;
+        na.acc = slot_ptr(h, h->pending + i);
+        hipError_t e = hipSuccess;
+        for (int half = 0; half < 2 && e == hipSuccess; ++half) {
+            uint8_t** from = half == 0 ? cur : oth;
+            uint8_t** to = half == 0 ? oth : cur;
+            na.src[0] = from[0];
+            na.src[1] = from[1];
+            na.dst[0] = to[0];
+            na.dst[1] = to[1];
+            na.launch = (uint32_t)(2 * t + (uint64_t)half);
+            e = launch_ne_sub(na, B, lam, h->stream);
+        }
+        sl_status st = SL_OK;
+        if (e == hipSuccess) {
+            st = enqueue_observe(h, h->pending + i);
+        } else {
+            st = hip_fail(e, "sub-lattice launch");
+        }
+        if (st != SL_OK) {
+            h->next_t += i;
+            h->pending += i;
+            return st;
+        }
+    }
+    h->next_t += n;
+    h->pending += n;
     return SL_OK;
 }
 
@@ -337,6 +407,7 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
     h->cur = 0;
     h->table_n = build_table(params, h->table);
     h->launch = auto_launch(h);
+    if (params->model == SL_NE_SUBLATTICE) h->launch = sl_launch{};
     h->stage = nullptr;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->stage),
                                  params->record_capacity * sizeof(sl_record), hipHostMallocDefault);
@@ -384,7 +455,7 @@ sl_status sl_set_launch(sl_lattice* h, const sl_launch* launch)
 {
     if (!h || !launch) return fail(SL_E_INVALID, "NULL argument");
     sl_launch l = *launch;
-    if (l.mode == SL_MODE_AUTO) l = auto_launch(h);
+    if (l.mode == SL_MODE_AUTO && h->params.model != SL_NE_SUBLATTICE) l = auto_launch(h);
     sl_status st = check_launch(h, &l);
     if (st != SL_OK) return st;
     h->launch = l;
@@ -406,8 +477,10 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
         return fail(SL_E_STATE, "%llu unread records + %llu sweeps exceed record_capacity %llu; "
                                 "call sl_measure first", (unsigned long long)h->pending,
                     (unsigned long long)n, (unsigned long long)h->params.record_capacity);
-    if (h->next_t + n > (1ull << 32))
-        return fail(SL_E_OVERFLOW, "sweep index would reach 2^32");
+    const uint64_t t_end = h->params.model == SL_NE_SUBLATTICE ? (1ull << 31) : (1ull << 32);
+    if (h->next_t + n > t_end)
+        return fail(SL_E_OVERFLOW, "sweep index would reach %llu", (unsigned long long)t_end);
+    if (h->params.model == SL_NE_SUBLATTICE) return sweep_ne_sub(h, n);
     SweepArgs a = args_of(h);
     for (uint64_t i = 0; i < n; ++i) {
         a.t = (uint32_t)(h->next_t + i);
@@ -503,7 +576,7 @@ sl_status sl_copy_spins(sl_lattice* h, int8_t* device_out, size_t n)
 sl_status sl_reset_persistence(sl_lattice* h)
 {
     if (!h) return fail(SL_E_INVALID, "NULL lattice");
-    if (h->params.model != SL_NORTH_EAST)
+    if (h->params.model == SL_ISING)
         return fail(SL_E_STATE, "persistence is tracked for the North-East model only");
     hipError_t e = launch_clear_flags(args_of(h), h->stream);
     if (e != hipSuccess) return hip_fail(e, "reset_persistence");

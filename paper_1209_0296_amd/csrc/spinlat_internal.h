@@ -65,4 +65,22 @@ hipError_t launch_row_half(const SweepArgs& a, int kind, int H, int D, hipStream
 hipError_t launch_row_fused(const SweepArgs& a, int kind, int H, int D, const uint8_t* src0,
                             const uint8_t* src1, uint8_t* dst0, uint8_t* dst1, hipStream_t s);
 
+// North-East model by random sub-lattices: one launch processes every B x B
+// sub-lattice once (q = B^2 / (2 lambda) iterations of lambda random sites),
+// reading `src` and writing `dst`.
+struct NeSubArgs {
+    const uint8_t* src[2];      // colour arrays at launch start
+    uint8_t* dst[2];            // colour arrays after the launch
+    uint32_t L, Lh, tiles_x, ntiles;
+    uint32_t key0, key1;        // Philox key = seed
+    uint32_t launch;            // 2 t for the first launch of sweep t, 2 t + 1 for the second
+    uint32_t wrap;              // 1 when one sub-lattice covers the lattice (B = L)
+    uint64_t thr_up, thr_down;  // NE thresholds in [0, 2^32]
+    unsigned long long* acc;    // record slot [kSub][kQ]
+};
+
+// B in {8, 16, 32, 64}, L % B == 0, lambda a power of two in [2, 128], 2 lambda <= B^2.
+bool ne_sub_supported(uint32_t L, int B, int lambda);
+hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, hipStream_t s);
+
 }  // namespace spinlat

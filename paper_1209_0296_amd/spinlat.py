@@ -17,8 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspinlat.so")
 
-ABI_VERSION = 1
-ISING, NORTH_EAST = 0, 1
+ABI_VERSION = 2
+ISING, NORTH_EAST, NE_SUBLATTICE = 0, 1, 2
 INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
 MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
 MODE_HALF_WINDOW, MODE_FUSED_WINDOW = 4, 5
@@ -49,6 +49,7 @@ class CParams(ctypes.Structure):
         ("J", ctypes.c_double), ("h", ctypes.c_double), ("T", ctypes.c_double),
         ("c", ctypes.c_double), ("seed", ctypes.c_uint64), ("t0", ctypes.c_uint64),
         ("record_capacity", ctypes.c_uint64), ("init_spins", ctypes.c_void_p),
+        ("ne_side", ctypes.c_int32), ("ne_lambda", ctypes.c_int32),
     ]
 
 
@@ -136,7 +137,9 @@ def _check(status: int) -> None:
 @dataclass
 class Params:
     """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1; 2D or
-    3D) or the North-East model (up-density c; 2D)."""
+    3D) or the North-East model (up-density c; 2D), by checkerboard half-sweeps
+    (NORTH_EAST) or by the random sub-lattice algorithm of Sec. 3.2
+    (NE_SUBLATTICE: side ``ne_side``, ``ne_lambda`` sites per iteration)."""
     model: int = ISING
     dim: int = 2
     L: int = 64
@@ -149,12 +152,14 @@ class Params:
     init: int = INIT_RANDOM
     t0: int = 0
     record_capacity: int = 1024
+    ne_side: int = 32
+    ne_lambda: int = 16
 
     def c_struct(self, init_spins_ptr: int = 0) -> CParams:
         return CParams(ABI_VERSION, self.model, self.dim, self.L, self.two_s, self.init,
                        float(self.J), float(self.h), float(self.T), float(self.c),
                        int(self.seed), int(self.t0), int(self.record_capacity),
-                       init_spins_ptr or None)
+                       init_spins_ptr or None, int(self.ne_side), int(self.ne_lambda))
 
     @property
     def nsites(self) -> int:

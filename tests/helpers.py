@@ -9,9 +9,11 @@ import paper_1209_0296_amd as S
 
 
 def oracle_params(sp: S.Params) -> O.Params:
-    return O.Params(model=sp.model, dim=sp.dim, L=sp.L, two_s=sp.two_s,
+    model = {S.ISING: O.ISING, S.NORTH_EAST: O.NORTH_EAST, S.NE_SUBLATTICE: O.NE_TILES}[sp.model]
+    return O.Params(model=model, dim=sp.dim, L=sp.L, two_s=sp.two_s,
                     init=O.INIT_COLD if sp.init == S.INIT_COLD else O.INIT_RANDOM,
-                    J=sp.J, h=sp.h, T=sp.T, c=sp.c, seed=sp.seed)
+                    J=sp.J, h=sp.h, T=sp.T, c=sp.c, seed=sp.seed,
+                    tile=sp.ne_side, lam=sp.ne_lambda)
 
 
 def run_oracle(sp: S.Params, nsweeps: int, start=None, nthreads: int = 0):

@@ -44,6 +44,12 @@ def _status(p):
     (dict(model=1, c=0.0), 1), (dict(model=1, c=1.0), 1), (dict(model=1, dim=3), 1),
     (dict(model=1, two_s=2), 1), (dict(model=1, init=S.INIT_COLD), 1), (dict(init=7), 1),
     (dict(t0=2 ** 32), 6), (dict(record_capacity=0), 1), (dict(model=7), 1),
+    # NE by random sub-lattices
+    (dict(model=2, L=72, ne_side=16), 1), (dict(model=2, L=64, ne_side=8, ne_lambda=3), 1),
+    (dict(model=2, L=64, ne_side=8, ne_lambda=64), 1), (dict(model=2, ne_side=0), 1),
+    (dict(model=2, L=64, ne_side=8, ne_lambda=1), 2), (dict(model=2, L=96, ne_side=12, ne_lambda=4), 2),
+    (dict(model=2, L=256, ne_side=128, ne_lambda=16), 2), (dict(model=2, ne_lambda=256), 2),
+    (dict(model=2, dim=3), 1), (dict(model=2, c=1.0), 1), (dict(model=2, t0=2 ** 31), 6),
 ])
 def test_invalid_parameters_rejected(kw, code):
     st, _ = _status(S.Params(**kw))
@@ -73,7 +79,7 @@ def test_infinite_temperature_allowed():
     dict(T=2.0), dict(T=2.269), dict(T=2.6), dict(T=0.3), dict(T=math.inf), dict(T=1.5, h=0.37),
     dict(T=1.1, J=-1.0, h=0.2), dict(dim=3, T=4.5115), dict(two_s=2, T=1.6935),
     dict(dim=3, two_s=2, T=3.19, h=-0.5), dict(model=1, c=0.05), dict(model=1, c=0.1),
-    dict(model=1, c=0.2), dict(model=1, c=0.7),
+    dict(model=1, c=0.2), dict(model=1, c=0.7), dict(model=2, c=0.42), dict(model=2, c=0.8),
 ])
 def test_threshold_table_equals_oracle(kw):
     p = S.Params(**kw)
@@ -112,3 +118,15 @@ def test_batch_shapes():
     for p in (S.Params(L=2056), S.Params(L=936), S.Params(L=64, T=0.05)):
         n = S.batch_job_bytes(p, cfg)
         assert n >= p.nsites
+
+
+@pytest.mark.parametrize("B,lam", [(8, 2), (8, 32), (16, 8), (32, 16), (32, 128), (64, 16), (64, 128)])
+def test_sub_lattice_shapes_accepted(B, lam):
+    assert _status(S.Params(model=S.NE_SUBLATTICE, L=128, ne_side=B, ne_lambda=lam))[0] == 0
+
+
+def test_sub_lattice_jobs_not_batched():
+    cfg = S.batch_config(max_jobs=4, record_capacity=8)
+    n = ctypes.c_size_t()
+    cp = S.Params(model=S.NE_SUBLATTICE, L=64).c_struct()
+    assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
