@@ -17,17 +17,29 @@
 // iteration precedes every write of it.  A workgroup is one wavefront holding
 // up to 64/(lambda/2) sub-lattices in LDS.
 //
-// LDS holds each sub-lattice in the colour-split form of the global layout:
-// for colour c, B+1 rows (row 0 = the north row, rows 1..B = the sub-lattice)
-// of B/2 bytes, plus one byte at index B/2 that holds the east column for the
-// sites whose east neighbour has colour c.  Rows then copy to and from HBM as
-// plain vectors, and a site's neighbours are found by index arithmetic.
+// LDS holds each sub-lattice in natural order: B+1 rows of stride S = B + 8
+// (row 0 = the north row, rows 1..B = the sub-lattice), with the east column
+// in column B.  A site's north and east neighbours are then at fixed offsets
+// (-S, +1) from it, so an attempt costs three byte reads from one address.
+// The colour-split rows of HBM are interleaved on the way in and split on the
+// way out.
 //
 // Accepted moves: the move sets n to 1-n and raises the "has flipped" flag
-// with LDS atomics on the containing 32-bit word (OR for an up-flip, AND then
-// OR for a down-flip).  The returned old value tells whether another attempt
-// of the same iteration already changed the site, so each changed site is
-// counted once, and a site drawn twice flips once.
+// with LDS atomics on the containing 32-bit word (AND clears n for a
+// down-flip, OR sets n for an up-flip and sets the flag).  Attempts of one
+// iteration on one site all see the same iteration-start n, so the value an
+// atomic returns tells whether another attempt already changed the site: each
+// changed site is counted once, and a site drawn twice flips once.  The four
+// atomics of a lane's two attempts are issued back to back (no-op masks for an
+// attempt that was not accepted).
+//
+// Latency: the Philox words of iteration j+1 do not depend on the lattice, so
+// they are computed while iteration j's LDS traffic is in flight.
+//
+// Records: the first launch of a sweep also measures the lattice it starts
+// from -- the state after the previous sweep -- from the sub-lattices it has
+// just loaded (bonds to the north and east neighbours, which tile the lattice's
+// bonds exactly once), so no separate pass reads the lattice for that record.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -45,11 +57,10 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 template <int B>
 struct SubLayout {
-    static constexpr int half = B / 2;                          // bytes of a colour row
-    static constexpr int stride = ((half + 1 + 15) / 16) * 16;  // LDS row stride
-    static constexpr int plane = (B + 1) * stride;              // one colour
-    static constexpr int bytes = 2 * plane;                     // one sub-lattice
-    static constexpr int unit = half < 16 ? half : 16;          // bytes per vector copy
+    static constexpr int half = B / 2;                  // bytes of a colour row
+    static constexpr int stride = B + 8;                // LDS row stride (8-byte aligned)
+    static constexpr int bytes = (B + 1) * stride;      // one sub-lattice with its boundary
+    static constexpr int unit = half < 16 ? half : 16;  // bytes of a colour vector copy
     static constexpr int units_per_row = half / unit;
 };
 
@@ -61,52 +72,118 @@ constexpr int tiles_per_wave()
 }
 
 template <int N>
-struct VecOf;
-template <>
-struct VecOf<4> {
-    using T = uint32_t;
-};
-template <>
-struct VecOf<8> {
-    using T = uint2;
-};
-template <>
-struct VecOf<16> {
-    using T = uint4;
+struct ColourVec {
+    uint32_t w[N / 4];
 };
 
-// Accepted move at LDS byte `idx` (word array w32) whose iteration-start
-// occupation is n: returns 1 if this call changed the site.
-__device__ __forceinline__ int flip_site(uint32_t* w32, uint32_t idx, uint32_t n)
+// Natural order from colour order: e holds the sites at even x, o those at
+// odd x (4 each); the result is the 8 sites in x order.
+__device__ __forceinline__ uint2 interleave(uint32_t e, uint32_t o)
 {
-    const uint32_t sh = (idx & 3u) * 8u;
-    uint32_t* p = w32 + (idx >> 2);
-    if (n == 0u) {
-        const uint32_t old = atomicOr(p, 3u << sh);  // n = 1, flag
-        return ((old >> sh) & 1u) == 0u ? 1 : 0;
-    }
-    const uint32_t old = atomicAnd(p, ~(1u << sh));  // n = 0
-    atomicOr(p, 2u << sh);                           // flag
-    return (int)((old >> sh) & 1u);
+    uint2 r;
+    r.x = (e & 0xFFu) | ((o & 0xFFu) << 8) | ((e & 0xFF00u) << 8) | ((o & 0xFF00u) << 16);
+    r.y = ((e >> 16) & 0xFFu) | ((o >> 8) & 0xFF00u) | ((e >> 8) & 0xFF0000u) | (o & 0xFF000000u);
+    return r;
 }
 
+__device__ __forceinline__ void split(uint2 v, uint32_t& e, uint32_t& o)
+{
+    e = (v.x & 0xFFu) | ((v.x >> 8) & 0xFF00u) | ((v.y & 0xFFu) << 16) | ((v.y << 8) & 0xFF000000u);
+    o = ((v.x >> 8) & 0xFFu) | ((v.x >> 16) & 0xFF00u) | ((v.y << 8) & 0xFF0000u) | (v.y & 0xFF000000u);
+}
+
+template <int N>
+__device__ __forceinline__ ColourVec<N> load_vec(const uint8_t* p)
+{
+    ColourVec<N> v;
+    if constexpr (N == 16) {
+        const uint4 q = *reinterpret_cast<const uint4*>(p);
+        v.w[0] = q.x; v.w[1] = q.y; v.w[2] = q.z; v.w[3] = q.w;
+    } else if constexpr (N == 8) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        v.w[0] = q.x; v.w[1] = q.y;
+    } else {
+        v.w[0] = *reinterpret_cast<const uint32_t*>(p);
+    }
+    return v;
+}
+
+template <int N>
+__device__ __forceinline__ void store_vec(uint8_t* p, const ColourVec<N>& v)
+{
+    if constexpr (N == 16) {
+        *reinterpret_cast<uint4*>(p) = make_uint4(v.w[0], v.w[1], v.w[2], v.w[3]);
+    } else if constexpr (N == 8) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(v.w[0], v.w[1]);
+    } else {
+        *reinterpret_cast<uint32_t*>(p) = v.w[0];
+    }
+}
+
+// Measurement of the sub-lattice as loaded (launch-start state): occupation,
+// bonds to the north and east neighbours, sites with the flag clear.
 template <int B, int LPT>
+__device__ __forceinline__ void observe_tile(const uint8_t* t, uint32_t l, int& mag, int& bond,
+                                             int& fresh)
+{
+    using Lay = SubLayout<B>;
+    constexpr int WPR = B / 4;  // 4-byte words per row
+    constexpr int NWORD = B * WPR;
+#pragma unroll
+    for (int i = 0; i < (NWORD + LPT - 1) / LPT; ++i) {
+        const int u = (int)l + i * LPT;
+        if (u < NWORD) {
+            const uint8_t* p = t + (1 + u / WPR) * Lay::stride + 4 * (u % WPR);
+            const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+            const uint32_t north = *reinterpret_cast<const uint32_t*>(p - Lay::stride);
+            const uint32_t next = *reinterpret_cast<const uint32_t*>(p + 4);
+            const uint32_t east = __builtin_amdgcn_alignbyte(next, v, 1);
+            const uint32_t nv = v & 0x01010101u;
+            mag += __builtin_popcount(nv);
+            bond += __builtin_popcount(nv & north) + __builtin_popcount(nv & east);
+            fresh += 4 - __builtin_popcount(v & 0x02020202u);
+        }
+    }
+}
+
+// LDS offsets of a site and of its north and east neighbours.
+template <int B, bool WRAP>
+__device__ __forceinline__ void site_offsets(uint32_t site, uint32_t& own, uint32_t& north,
+                                             uint32_t& east)
+{
+    constexpr int S = SubLayout<B>::stride;
+    constexpr int LOGB = ilog2(B);
+    const uint32_t r = site >> LOGB;
+    if constexpr (!WRAP) {
+        north = site + r * (S - B);  // r * S + c
+        own = north + S;
+        east = own + 1;
+    } else {  // one sub-lattice: the periodic neighbours are inside it
+        const uint32_t c = site & (B - 1);
+        own = (r + 1) * S + c;
+        north = (r == 0 ? (uint32_t)B : r) * S + c;
+        east = (r + 1) * S + (c == B - 1 ? 0u : c + 1);
+    }
+}
+
+template <int B, int LPT, bool WRAP>
 __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
 {
     using Lay = SubLayout<B>;
-    using V = typename VecOf<Lay::unit>::T;
+    constexpr int S = Lay::stride;
+    constexpr int UNIT = Lay::unit;
     constexpr int TPW = tiles_per_wave<B, LPT>();
     constexpr int LOGB = ilog2(B);
     constexpr int QIT = B * B / (4 * LPT);  // q = P / (2 lambda), lambda = 2 LPT
-    constexpr int NU = 2 * (B + 1) * Lay::units_per_row;  // vector copies per load
-    constexpr int NW = 2 * B * Lay::units_per_row;        // vector copies per store
+    constexpr int NU = (B + 1) * Lay::units_per_row;  // colour-vector pairs per load
+    constexpr int NW = B * Lay::units_per_row;        // colour-vector pairs per store
     __shared__ __align__(16) uint8_t lds[TPW * Lay::bytes];
 
     const uint32_t lane = threadIdx.x;
     const uint32_t g = lane / LPT;
     const uint32_t l = lane % LPT;
     const uint32_t tau = blockIdx.x * TPW + g;
-    int changed = 0;
+    int changed = 0, mag = 0, bond = 0, fresh = 0;
     if (g < (uint32_t)TPW && tau < a.ntiles) {
         uint8_t* t = lds + g * Lay::bytes;
         const uint32_t tx = tau % a.tiles_x, ty = tau / a.tiles_x;
@@ -114,18 +191,21 @@ __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
         const uint32_t ynorth = y0 == 0 ? a.L - 1 : y0 - 1;
         const size_t kx = x0 >> 1;
 
-        // north row and sub-lattice rows of both colours
+        // north row and sub-lattice rows: both colours, interleaved
 #pragma unroll
         for (int i = 0; i < (NU + LPT - 1) / LPT; ++i) {
             const int u = (int)l + i * LPT;
             if (u < NU) {
-                const int c = u / ((B + 1) * Lay::units_per_row);
-                const int rem = u % ((B + 1) * Lay::units_per_row);
-                const int pr = rem / Lay::units_per_row, part = rem % Lay::units_per_row;
+                const int pr = u / Lay::units_per_row, part = u % Lay::units_per_row;
                 const uint32_t y = pr == 0 ? ynorth : y0 + pr - 1;
-                const V v = *reinterpret_cast<const V*>(a.src[c] + (size_t)y * a.Lh + kx +
-                                                        part * Lay::unit);
-                *reinterpret_cast<V*>(t + c * Lay::plane + pr * Lay::stride + part * Lay::unit) = v;
+                const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
+                const ColourVec<UNIT> c0 = load_vec<UNIT>(a.src[0] + off);
+                const ColourVec<UNIT> c1 = load_vec<UNIT>(a.src[1] + off);
+                const bool odd = (y & 1u) != 0;  // colour 1 holds the even x of odd rows
+                uint2* dstp = reinterpret_cast<uint2*>(t + pr * S + part * 2 * UNIT);
+#pragma unroll
+                for (int k = 0; k < UNIT / 4; ++k)
+                    dstp[k] = odd ? interleave(c1.w[k], c0.w[k]) : interleave(c0.w[k], c1.w[k]);
             }
         }
         // east column: site (x0 + B, y) has colour (x0 + B + y) & 1
@@ -135,51 +215,84 @@ __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
             const int r = (int)l + i * LPT;
             if (r < B) {
                 const uint32_t y = y0 + r;
-                const uint32_t c = (xe + y) & 1u;
-                t[c * Lay::plane + (r + 1) * Lay::stride + Lay::half] =
-                    a.src[c][(size_t)y * a.Lh + (xe >> 1)];
+                t[(r + 1) * S + B] = a.src[(xe + y) & 1u][(size_t)y * a.Lh + (xe >> 1)];
             }
         }
+
+        if (a.obs) observe_tile<B, LPT>(t, l, mag, bond, fresh);
 
         const PhiloxKey ks = philox_schedule(a.key0, a.key1);
         uint32_t* w32 = reinterpret_cast<uint32_t*>(t);
-        const bool wrap = a.wrap != 0;
+        Words4 w = philox4x32_10(tau, l, a.launch, kTagNeSub, ks);
         for (int j = 0; j < QIT; ++j) {
-            const Words4 w = philox4x32_10(tau, (uint32_t)j * LPT + l, a.launch, kTagNeSub, ks);
-            uint32_t idx[2], nv[2];
+            uint32_t own[2], nocc[2], vs[2], vn[2], ve[2], acc_word[2];
             bool ok[2];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                const uint32_t site = w.w[2 * m] >> (32 - 2 * LOGB);  // floor(word P / 2^32)
-                const uint32_t r = site >> LOGB, cc = site & (B - 1);
-                const uint32_t cs = (cc ^ r) & 1u;  // colour of (x0+cc, y0+r)
-                const uint32_t own = cs * Lay::plane, oth = (cs ^ 1u) * Lay::plane;
-                idx[m] = own + (r + 1) * Lay::stride + (cc >> 1);
-                const uint32_t rn = (wrap && r == 0) ? (uint32_t)B : r;
-                const uint32_t ce = (wrap && cc == B - 1) ? 0u : cc + 1;
-                const uint32_t n = t[idx[m]] & 1u;
-                const uint32_t north = t[oth + rn * Lay::stride + (cc >> 1)];
-                const uint32_t east = t[oth + (r + 1) * Lay::stride + (ce >> 1)];
-                const uint64_t thr = n ? a.thr_down : a.thr_up;
-                ok[m] = ((north & east & 1u) != 0u) && ((uint64_t)w.w[2 * m + 1] < thr);
-                nv[m] = n;
+                uint32_t north, east;
+                site_offsets<B, WRAP>(w.w[2 * m] >> (32 - 2 * LOGB), own[m], north, east);
+                vs[m] = t[own[m]];
+                vn[m] = t[north];
+                ve[m] = t[east];
+                acc_word[m] = w.w[2 * m + 1];
             }
+            // next iteration's words while the reads are in flight; the empty
+            // asm pins them here (the compiler would otherwise sink them past
+            // the atomics, where they would wait for the atomics' results)
+            w = philox4x32_10(tau, (uint32_t)(j + 1) * LPT + l, a.launch, kTagNeSub, ks);
+            asm volatile("" : "+v"(w.w[0]), "+v"(w.w[1]), "+v"(w.w[2]), "+v"(w.w[3]));
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
-                if (ok[m]) changed += flip_site(w32, idx[m], nv[m]);
+            for (int m = 0; m < 2; ++m) {
+                const uint32_t n = vs[m] & 1u;
+                const uint32_t allow = vn[m] & ve[m] & 1u;
+                // accept iff word < thr, thr in [0, 2^32]: word <= thr - 1 unless thr = 0
+                const uint32_t thr_m1 = n ? a.thr_m1_down : a.thr_m1_up;
+                const uint32_t never = (a.never >> n) & 1u;
+                ok[m] = (allow & (acc_word[m] <= thr_m1 ? 1u : 0u) & (never ^ 1u)) != 0u;
+                nocc[m] = n;
+            }
+            if (ok[0] | ok[1]) {
+                uint32_t sh[2], old_and[2], old_or[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    sh[m] = (own[m] & 3u) * 8u;
+                    const bool dn = ok[m] & (nocc[m] != 0u);
+                    old_and[m] = atomicAnd(w32 + (own[m] >> 2), dn ? ~(1u << sh[m]) : ~0u);
+                }
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const uint32_t set = ok[m] ? (nocc[m] ? 2u : 3u) : 0u;
+                    old_or[m] = atomicOr(w32 + (own[m] >> 2), set << sh[m]);
+                }
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    // first change of the site in this iteration: n still as at its start
+                    const uint32_t before = nocc[m] ? old_and[m] : old_or[m];
+                    changed += (int)(ok[m] & (((before >> sh[m]) & 1u) == nocc[m]));
+                }
+            }
         }
 
-        // the sub-lattice rows of both colours back to HBM
+        // the sub-lattice rows back to HBM, split into colours
 #pragma unroll
         for (int i = 0; i < (NW + LPT - 1) / LPT; ++i) {
             const int u = (int)l + i * LPT;
             if (u < NW) {
-                const int c = u / (B * Lay::units_per_row);
-                const int rem = u % (B * Lay::units_per_row);
-                const int r = rem / Lay::units_per_row, part = rem % Lay::units_per_row;
-                const V v = *reinterpret_cast<const V*>(t + c * Lay::plane + (r + 1) * Lay::stride +
-                                                        part * Lay::unit);
-                *reinterpret_cast<V*>(a.dst[c] + (size_t)(y0 + r) * a.Lh + kx + part * Lay::unit) = v;
+                const int r = u / Lay::units_per_row, part = u % Lay::units_per_row;
+                const uint32_t y = y0 + r;
+                const uint2* srcp = reinterpret_cast<const uint2*>(t + (r + 1) * S + part * 2 * UNIT);
+                ColourVec<UNIT> c0, c1;
+                const bool odd = (y & 1u) != 0;
+#pragma unroll
+                for (int k = 0; k < UNIT / 4; ++k) {
+                    uint32_t e, o;
+                    split(srcp[k], e, o);
+                    c0.w[k] = odd ? o : e;
+                    c1.w[k] = odd ? e : o;
+                }
+                const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
+                store_vec<UNIT>(a.dst[0] + off, c0);
+                store_vec<UNIT>(a.dst[1] + off, c1);
             }
         }
     }
@@ -187,6 +300,18 @@ __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
     for (int off = 32; off > 0; off >>= 1) changed += __shfl_xor(changed, off, 64);
     if (lane == 0 && changed != 0)
         atomicAdd(&a.acc[(blockIdx.x % kSub) * kQ + 2], (unsigned long long)changed);
+    if (a.obs) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mag += __shfl_xor(mag, off, 64);
+            bond += __shfl_xor(bond, off, 64);
+            fresh += __shfl_xor(fresh, off, 64);
+        }
+        unsigned long long* o = a.obs + (blockIdx.x % kSub) * kQ;
+        if (lane == 0 && bond != 0) atomicAdd(&o[0], (unsigned long long)bond);
+        if (lane == 1 && mag != 0) atomicAdd(&o[1], (unsigned long long)mag);
+        if (lane == 2 && fresh != 0) atomicAdd(&o[3], (unsigned long long)fresh);
+    }
 }
 
 template <int B, int LPT>
@@ -195,7 +320,10 @@ hipError_t launch_one(const NeSubArgs& a, hipStream_t s)
     constexpr int TPW = tiles_per_wave<B, LPT>();
     static_assert(TPW >= 1, "a sub-lattice must fit the LDS budget");
     const uint32_t blocks = (a.ntiles + TPW - 1) / TPW;
-    hipLaunchKernelGGL((k_ne_sub<B, LPT>), dim3(blocks), dim3(64), 0, s, a);
+    if (a.ntiles == 1)
+        hipLaunchKernelGGL((k_ne_sub<B, LPT, true>), dim3(blocks), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_ne_sub<B, LPT, false>), dim3(blocks), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -304,9 +304,10 @@ sl_status enqueue_observe(sl_lattice* h, uint64_t slot)
 
 // Paper Sec. 3.2, NE algorithm with random sub-lattices: per sweep, launch
 // 2t reads the current copy and writes the other, launch 2t+1 reads that and
-// writes the current copy back; the record of the sweep is then observed
-// from the current copy (both colours, no update) into the same slot the two
-// launches added their accepted counts to.
+// writes the current copy back.  Both add their accepted counts to the
+// sweep's record slot.  The lattice part of a sweep's record is measured by
+// the first launch of the next sweep from the state it loads; after the last
+// sweep of the call a separate pass (both colours, no update) measures it.
 sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
 {
     const int B = h->params.ne_side, lam = h->params.ne_lambda;
@@ -318,9 +319,10 @@ sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
     na.ntiles = na.tiles_x * na.tiles_x;
     na.key0 = (uint32_t)h->params.seed;
     na.key1 = (uint32_t)(h->params.seed >> 32);
-    na.wrap = na.tiles_x == 1 ? 1u : 0u;
-    na.thr_up = h->table[0];
-    na.thr_down = h->table[1];
+    // thresholds in [0, 2^32] as 32-bit "word <= thr - 1" with a flag for 0
+    na.thr_m1_up = h->table[0] ? (uint32_t)(h->table[0] - 1) : 0u;
+    na.thr_m1_down = h->table[1] ? (uint32_t)(h->table[1] - 1) : 0u;
+    na.never = (h->table[0] == 0 ? 1u : 0u) | (h->table[1] == 0 ? 2u : 0u);
     uint8_t* cur[2] = {h->base + h->lay.off_col[h->cur][0], h->base + h->lay.off_col[h->cur][1]};
     uint8_t* oth[2] = {h->base + h->lay.off_col[h->cur ^ 1][0],
                        h->base + h->lay.off_col[h->cur ^ 1][1]};
@@ -336,13 +338,15 @@ sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
             na.dst[0] = to[0];
             na.dst[1] = to[1];
             na.launch = (uint32_t)(2 * t + (uint64_t)half);
+            na.obs = (half == 0 && i > 0) ? slot_ptr(h, h->pending + i - 1) : nullptr;
             e = launch_ne_sub(na, B, lam, h->stream);
         }
         sl_status st = SL_OK;
-        if (e == hipSuccess) {
-            st = enqueue_observe(h, h->pending + i);
-        } else {
+        if (e != hipSuccess) {
             st = hip_fail(e, "sub-lattice launch");
+            if (i > 0) (void)enqueue_observe(h, h->pending + i - 1);
+        } else if (i + 1 == n) {
+            st = enqueue_observe(h, h->pending + i);
         }
         if (st != SL_OK) {
             h->next_t += i;

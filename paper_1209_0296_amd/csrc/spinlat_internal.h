@@ -74,9 +74,12 @@ struct NeSubArgs {
     uint32_t L, Lh, tiles_x, ntiles;
     uint32_t key0, key1;        // Philox key = seed
     uint32_t launch;            // 2 t for the first launch of sweep t, 2 t + 1 for the second
-    uint32_t wrap;              // 1 when one sub-lattice covers the lattice (B = L)
-    uint64_t thr_up, thr_down;  // NE thresholds in [0, 2^32]
-    unsigned long long* acc;    // record slot [kSub][kQ]
+    uint32_t thr_m1_up;         // NE up-flip threshold minus one (accept iff word <= it)
+    uint32_t thr_m1_down;       // NE down-flip threshold minus one
+    uint32_t never;             // bit 0: up-flip threshold is 0; bit 1: down-flip threshold is 0
+    unsigned long long* acc;    // record slot [kSub][kQ] of this sweep (accepted)
+    unsigned long long* obs;    // if set: record slot that receives bond_sum, mag and
+                                // unflipped of the launch-start lattice
 };
 
 // B in {8, 16, 32, 64}, L % B == 0, lambda a power of two in [2, 128], 2 lambda <= B^2.
