@@ -28,33 +28,42 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
-KERNEL_SOURCES = ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
-                  "spinlat_internal.h")
+# sources of the profiled kernels, hashed into profiles/traffic.json
+KERNEL_SOURCES = {
+    "ising2d_L8192": ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
+                      "spinlat_internal.h"),
+    "ne2d_sub_L4096": ("kernels_ne_sub.hip", "philox.hpp", "spinlat_internal.h"),
+}
+
+
+def sources_sha256(workload):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[workload]:
+        with open(os.path.join(ROOT, "paper_1209_0296_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE profile,
     or None when the kernel sources changed since the counters were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     entry = json.load(open(path)).get(workload)
     if not entry:
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1209_0296_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return entry["bytes_per_launch"] if h.hexdigest() == entry["sources_sha256"] else None
+    return entry["bytes_per_launch"] if sources_sha256(workload) == entry["sources_sha256"] else None
 
 
 def _lattice(S, cfg, T=None, record_capacity=4096):
     p = S.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
                  J=cfg.get("J", 1.0), h=cfg.get("h", 0.0), T=T if T is not None else cfg.get("T", 1.0),
                  c=cfg.get("c", 0.1), seed=cfg["seed"], init=cfg["init"],
-                 record_capacity=record_capacity)
+                 record_capacity=record_capacity, ne_side=cfg.get("ne_side", 32),
+                 ne_lambda=cfg.get("ne_lambda", 16))
     return p, S.Lattice(p)
 
 
@@ -79,9 +88,14 @@ def time_workload(S, torch, name, cfg, steps, warmup, T=None):
     mode = lat.get_launch()
     lat.close()
     attempts = p.nsites * steps
-    launches_per_sweep = 1 if mode[0] == S.MODE_FUSED else 2
+    if p.model == S.NE_SUBLATTICE:
+        # two launches per sweep, each reading and writing the whole lattice
+        launches_per_sweep = 2
+        bytes_per_launch = 2 * p.nsites
+    else:
+        launches_per_sweep = 1 if mode[0] == S.MODE_FUSED else 2
+        bytes_per_launch = ALGO_BYTES_PER_ATTEMPT * p.nsites / launches_per_sweep
     per_launch_s = sweep_ms / 1e3 / (steps * launches_per_sweep)
-    bytes_per_launch = ALGO_BYTES_PER_ATTEMPT * p.nsites / launches_per_sweep
     achieved = bytes_per_launch / per_launch_s / 1e9
     return {
         "workload": name, "attempts_per_s": attempts / wall, "wall_s": wall,
@@ -152,7 +166,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-secondary", action="store_true", help="skip the 3D L=256 line")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 3D L=256 and NE L=4096 lines")
     ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--served-jobs", type=int, default=4096,
                     help="jobs in the served Poisson stream (0: skip serving)")
@@ -160,6 +175,9 @@ def main():
     ap.add_argument("--served-arena-mib", type=int, default=512)
     ap.add_argument("--compare-jobs", type=int, default=48,
                     help="jobs served both batched and one run per launch (closed batch)")
+    ap.add_argument("--only", default="", metavar="WORKLOAD",
+                    help="time only this workload of workloads.CONFIGS and print its own JSON "
+                         "line (for profiling one kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -185,13 +203,18 @@ def main():
     import paper_1209_0296_amd as S
     from workloads import CONFIGS
 
+    if args.only:
+        r = time_workload(S, torch, args.only, CONFIGS[args.only], args.steps, args.warmup)
+        print(json.dumps(r), flush=True)
+        return
+
     cfg2 = CONFIGS["ising2d_L8192"]
     main_res = time_workload(S, torch, "ising2d_L8192_T2.269", cfg2, args.steps, args.warmup)
     print(f"# 2D L=8192: {main_res['attempts_per_s']:.4g} attempts/s, "
           f"{main_res['ms_per_step']:.4f} ms/sweep", file=sys.stderr, flush=True)
     secondary = []
     if not args.no_secondary:
-        for key in ("ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096"):
+        for key in ("ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096", "ne2d_sub_L4096"):
             r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)
