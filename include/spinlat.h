@@ -271,6 +271,41 @@ sl_status sl_batch_remove(sl_batch* b, uint32_t job_id);
 /* Release the batch (never frees the arena).  Synchronises. */
 sl_status sl_batch_destroy(sl_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Observables of a run (paper Sec. 5: magnetisation, energy and heat capacity
+ * against temperature, Fig. 6; Eq. 4: the NE spin autocorrelation).
+ * ------------------------------------------------------------------------- */
+typedef struct sl_stats {
+    uint64_t n;            /* records averaged */
+    double e;              /* <e>, e = (-J bond_sum - h mag) / N, energy per site */
+    double e_var;          /* <(e - <e>)^2> */
+    double m;              /* <m>, m = mag / N */
+    double m_abs;          /* <|m|> */
+    double m2;             /* <m^2> */
+    double m4;             /* <m^4> */
+    double heat_capacity;  /* per site, N <(e - <e>)^2> / T^2 (k_B = 1) */
+    double susceptibility; /* per site, N (<m^2> - <|m|>^2) / T */
+    double binder;         /* 1 - <m^4> / (3 <m^2>^2); NaN if <m^2> = 0 */
+} sl_stats;
+
+/* Means over records[0..n) of an Ising run (host-only, pure, double precision;
+ * the caller leaves out the records before equilibrium).  SL_E_INVALID for
+ * n == 0 or NE parameters. */
+sl_status sl_record_statistics(const sl_params* params, const sl_record* records, size_t n,
+                               sl_stats* out);
+
+/* Overlap sum_i v_i(t) v_i^ref of the current lattice with a reference lattice
+ * (device pointer, L^dim bytes in natural order as sl_copy_spins writes them,
+ * e.g. the state at the time origin): v = s for Ising, v = 2n - 1 for an NE
+ * occupation n (flag bits ignored).  Synchronises the stream; the result is
+ * written to *overlap on the host. */
+sl_status sl_overlap(sl_lattice* lat, const int8_t* reference, int64_t* overlap);
+
+/* NE spin autocorrelation of Eq. 4 from an overlap: Phi = (overlap / N -
+ * <s>^2) / (1 - <s>^2) with <s> = 2c - 1 (host-only, pure).  SL_E_INVALID for
+ * Ising parameters. */
+sl_status sl_autocorrelation(const sl_params* params, int64_t overlap, double* phi);
+
 const char* sl_status_str(sl_status status);
 const char* sl_last_error(void);
 

@@ -93,6 +93,37 @@ __global__ void __launch_bounds__(kBlock) k_to_natural(SweepArgs a, int8_t* nat)
         nat[natural_index(a.g, c, 4 * g + b)] = (int8_t)(uint8_t)(word >> (8 * b));
 }
 
+// Overlap sum_i v_i v_i^ref with a natural-order reference lattice (v = s for
+// Ising, 2n - 1 for an NE occupation n), accumulated into one int64.
+__global__ void __launch_bounds__(kBlock) k_overlap(SweepArgs a, const int8_t* ref, int ne,
+                                                    unsigned long long* out)
+{
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t sum = 0;
+    if (gi < 2 * ngroups) {
+        const uint32_t c = gi >= ngroups ? 1u : 0u;
+        const uint64_t g = gi - (c ? ngroups : 0);
+        const uint32_t word = *reinterpret_cast<const uint32_t*>(a.col[c] + 4 * g);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int v = (int)(int8_t)(uint8_t)(word >> (8 * b));
+            const int r = (int)ref[natural_index(a.g, c, 4 * g + b)];
+            sum += ne ? (2 * (v & 1) - 1) * (2 * (r & 1) - 1) : v * r;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    __shared__ int32_t part[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        if (t != 0) atomicAdd(out, (unsigned long long)t);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_clear_flags(SweepArgs a)
 {
     const uint64_t ngroups = a.g.nh >> 2;
@@ -259,6 +290,14 @@ hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_natural, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a,
                        nat);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap(const SweepArgs& a, const int8_t* ref, int ne, unsigned long long* out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_overlap, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a, ref,
+                       ne, out);
     return hipGetLastError();
 }
 

@@ -617,6 +617,76 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
     return SL_OK;
 }
 
+sl_status sl_record_statistics(const sl_params* params, const sl_record* records, size_t n,
+                               sl_stats* out)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK && st != SL_E_UNSUPPORTED) return st;
+    if (params->model != SL_ISING)
+        return fail(SL_E_INVALID, "thermodynamic statistics are defined for the Ising model");
+    if (n == 0 || !records || !out) return fail(SL_E_INVALID, "need n >= 1 records and an output");
+    const double N = (double)layout_of(params).nsites;
+    const double inv_n = 1.0 / (double)n;
+    double se = 0.0, sm = 0.0, sma = 0.0, sm2 = 0.0, sm4 = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double e = (-params->J * (double)records[i].bond_sum - params->h * (double)records[i].mag) / N;
+        const double m = (double)records[i].mag / N;
+        se += e;
+        sm += m;
+        sma += std::fabs(m);
+        sm2 += m * m;
+        sm4 += (m * m) * (m * m);
+    }
+    const double mean_e = se * inv_n;
+    double sv = 0.0;  // second pass: variance of e
+    for (size_t i = 0; i < n; ++i) {
+        const double e = (-params->J * (double)records[i].bond_sum - params->h * (double)records[i].mag) / N;
+        sv += (e - mean_e) * (e - mean_e);
+    }
+    sl_stats r{};
+    r.n = n;
+    r.e = mean_e;
+    r.e_var = sv * inv_n;
+    r.m = sm * inv_n;
+    r.m_abs = sma * inv_n;
+    r.m2 = sm2 * inv_n;
+    r.m4 = sm4 * inv_n;
+    r.heat_capacity = N * r.e_var / (params->T * params->T);
+    r.susceptibility = N * (r.m2 - r.m_abs * r.m_abs) / params->T;
+    r.binder = r.m2 > 0.0 ? 1.0 - r.m4 / (3.0 * r.m2 * r.m2) : std::nan("");
+    *out = r;
+    return SL_OK;
+}
+
+sl_status sl_overlap(sl_lattice* h, const int8_t* reference, int64_t* overlap)
+{
+    if (!h || !reference || !overlap) return fail(SL_E_INVALID, "NULL argument");
+    // the first folded-record slot serves as the accumulator: sl_measure
+    // rewrites that area from the ring before it reads it
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(h->base + h->lay.off_out);
+    hipError_t e = launch_fill_u64(acc, 1, h->stream);
+    if (e == hipSuccess) e = launch_overlap(args_of(h), reference, h->kind == KIND_NE ? 1 : 0, acc, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->stage, acc, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "overlap");
+    std::memcpy(overlap, h->stage, sizeof(int64_t));
+    return SL_OK;
+}
+
+sl_status sl_autocorrelation(const sl_params* params, int64_t overlap, double* phi)
+{
+    sl_status st = validate(params);
+    if (st != SL_OK && st != SL_E_UNSUPPORTED) return st;
+    if (params->model == SL_ISING)
+        return fail(SL_E_INVALID, "Phi(t) of Eq. 4 is defined for the North-East model");
+    if (!phi) return fail(SL_E_INVALID, "phi is NULL");
+    const double N = (double)layout_of(params).nsites;
+    const double m0 = 2.0 * params->c - 1.0;
+    *phi = ((double)overlap / N - m0 * m0) / (1.0 - m0 * m0);
+    return SL_OK;
+}
+
 const char* sl_status_str(sl_status s)
 {
     switch (s) {

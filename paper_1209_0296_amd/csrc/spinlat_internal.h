@@ -48,6 +48,9 @@ hipError_t launch_init(const SweepArgs& a, int kind, int init_mode, uint32_t ber
 hipError_t launch_from_natural(const SweepArgs& a, const int8_t* nat, hipStream_t s);
 hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s);
 hipError_t launch_clear_flags(const SweepArgs& a, hipStream_t s);
+// out (one int64, zeroed by the caller) += sum_i v_i v_i^ref; ne: v = 2n - 1
+hipError_t launch_overlap(const SweepArgs& a, const int8_t* ref, int ne, unsigned long long* out,
+                          hipStream_t s);
 hipError_t launch_simple_half(const SweepArgs& a, int kind, hipStream_t s);
 hipError_t launch_tiled_half(const SweepArgs& a, int kind, hipStream_t s);
 hipError_t launch_fused_sweep(const SweepArgs& a, int kind, const uint8_t* src0, const uint8_t* src1,

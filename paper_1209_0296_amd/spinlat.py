@@ -33,6 +33,7 @@ EXPORTS = (
     "sl_record_observables", "sl_batch_job_bytes", "sl_batch_base_bytes", "sl_batch_create",
     "sl_batch_add", "sl_batch_sweep", "sl_batch_job_status", "sl_batch_measure",
     "sl_batch_copy_spins", "sl_batch_remove", "sl_batch_destroy", "sl_batch_drain",
+    "sl_record_statistics", "sl_overlap", "sl_autocorrelation",
 )
 
 
@@ -62,6 +63,13 @@ class CBatchConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("max_jobs", ctypes.c_uint32),
                 ("record_capacity", ctypes.c_uint32), ("tile_rows", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_uint64)]
+
+
+class CStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("e", ctypes.c_double), ("e_var", ctypes.c_double),
+                ("m", ctypes.c_double), ("m_abs", ctypes.c_double), ("m2", ctypes.c_double),
+                ("m4", ctypes.c_double), ("heat_capacity", ctypes.c_double),
+                ("susceptibility", ctypes.c_double), ("binder", ctypes.c_double)]
 
 
 class CLaunch(ctypes.Structure):
@@ -121,6 +129,9 @@ def lib():
     L.sl_batch_drain.argtypes = [B, ctypes.c_void_p, ctypes.c_void_p, sz, ctypes.POINTER(sz)]
     L.sl_batch_remove.argtypes = [B, ctypes.c_uint32]
     L.sl_batch_destroy.argtypes = [B]
+    L.sl_record_statistics.argtypes = [P, ctypes.c_void_p, sz, ctypes.POINTER(CStats)]
+    L.sl_overlap.argtypes = [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    L.sl_autocorrelation.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sl_status_str", "sl_last_error"):
@@ -275,6 +286,15 @@ class Lattice:
     def reset_persistence(self) -> None:
         _check(lib().sl_reset_persistence(self._h))
 
+    def overlap(self, reference) -> int:
+        """sum_i v_i v_i^ref with a device int8 tensor in natural order (synchronises)."""
+        ref = reference.to(device=self.device, dtype=self._torch.int8).contiguous()
+        if ref.numel() != self.params.nsites:
+            raise ValueError("reference has the wrong size")
+        out = ctypes.c_int64()
+        _check(lib().sl_overlap(self._h, ref.data_ptr(), ctypes.byref(out)))
+        return int(out.value)
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             _check(lib().sl_destroy(self._h))
@@ -291,6 +311,30 @@ class Lattice:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def record_statistics(p: Params, records) -> dict:
+    """Means, heat capacity, susceptibility and Binder cumulant of Ising records
+    (structured records or an (n, 5) int64 array), computed by the library."""
+    recs = np.ascontiguousarray(records)
+    if recs.dtype != RECORD_DTYPE:
+        a = np.asarray(recs, dtype=np.int64)
+        recs = np.zeros(len(a), dtype=RECORD_DTYPE)
+        for i, f in enumerate(RECORD_DTYPE.names):
+            recs[f] = a[:, i]
+    st = CStats()
+    cp = p.c_struct(1 if p.init == INIT_BUFFER else 0)
+    _check(lib().sl_record_statistics(ctypes.byref(cp), recs.ctypes.data, len(recs),
+                                      ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in CStats._fields_}
+
+
+def autocorrelation(p: Params, overlap: int) -> float:
+    """NE spin autocorrelation Phi (Eq. 4) of an overlap, computed by the library."""
+    phi = ctypes.c_double()
+    cp = p.c_struct(1 if p.init == INIT_BUFFER else 0)
+    _check(lib().sl_autocorrelation(ctypes.byref(cp), int(overlap), ctypes.byref(phi)))
+    return phi.value
 
 
 def records_to_array(records: np.ndarray) -> np.ndarray:

@@ -130,3 +130,47 @@ def test_sub_lattice_jobs_not_batched():
     n = ctypes.c_size_t()
     cp = S.Params(model=S.NE_SUBLATTICE, L=64).c_struct()
     assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
+
+
+def _records_from(rec):
+    out = np.zeros(len(rec), dtype=S.RECORD_DTYPE)
+    for i, f in enumerate(S.RECORD_DTYPE.names):
+        out[f] = rec[:, i]
+    return out
+
+
+@pytest.mark.parametrize("kw", [dict(L=64, T=2.269), dict(L=64, T=2.6, h=0.1, J=0.8),
+                                dict(dim=3, L=16, T=4.5)])
+def test_record_statistics_equal_oracle(kw):
+    """sl_record_statistics against the oracle's statistics on oracle records."""
+    from oracle import observables as OB
+
+    p = S.Params(seed=9, **kw)
+    op = oracle_params(p)
+    s = O.init_lattice(op)
+    rec = O.run(op, s, 0, 400)
+    got = S.record_statistics(p, _records_from(rec))
+    want = OB.statistics(op, rec)
+    for k in ("e", "e_var", "m", "m_abs", "m2", "m4", "heat_capacity", "susceptibility", "binder"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-14), k
+    assert got["n"] == 400
+
+
+def test_record_statistics_errors():
+    p = S.Params(model=S.NORTH_EAST)
+    with pytest.raises(S.SpinlatError):
+        S.record_statistics(p, np.zeros((3, 5), dtype=np.int64))
+    with pytest.raises(S.SpinlatError):
+        S.record_statistics(S.Params(), np.zeros((0, 5), dtype=np.int64))
+
+
+def test_autocorrelation_equals_oracle():
+    from oracle import observables as OB
+
+    for model in (S.NORTH_EAST, S.NE_SUBLATTICE):
+        p = S.Params(model=model, L=64, c=0.3)
+        op = oracle_params(p)
+        for ov in (4096, 1000, -37, 0):
+            assert S.autocorrelation(p, ov) == pytest.approx(OB.autocorrelation(op, ov), rel=1e-15)
+    with pytest.raises(S.SpinlatError):
+        S.autocorrelation(S.Params(), 10)
