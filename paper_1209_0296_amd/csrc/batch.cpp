@@ -415,12 +415,12 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     // the staging buffers are rewritten by the next call: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     // one launch per colour for every job (the work list is grouped by
-    // variant), then the counter advance
-    for (uint64_t s = 0; s < n_eff && e == hipSuccess; ++s) {
+    // variant); sweep s of the call runs sweep t + s of the jobs with more
+    // than s sweeps in this call
+    for (uint64_t s = 0; s < n_eff && e == hipSuccess; ++s)
         for (uint32_t colour = 0; colour < 2 && e == hipSuccess; ++colour)
-            e = launch_batch_all(d_jobs(b), d_dyn(b), d_wgs(b), (uint32_t)nwg, colour, b->stream);
-        if (e == hipSuccess) e = launch_batch_advance(d_dyn(b), top, b->stream);
-    }
+            e = launch_batch_all(d_jobs(b), d_dyn(b), d_wgs(b), (uint32_t)nwg, colour, (uint32_t)s,
+                                 b->stream);
     (void)classes;
     if (e != hipSuccess) return hip_fail(e, "batch sweep");
     for (uint32_t j = 0; j < top; ++j) {

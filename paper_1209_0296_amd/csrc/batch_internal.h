@@ -8,7 +8,7 @@
 
 namespace spinlat {
 
-constexpr int kDynWords = 4;  // per job: {t, record slot, sweeps left, unused}
+constexpr int kDynWords = 4;  // per job: {t, record slot, sweeps in this call, unused}
 constexpr int kTableMax = 52; // Ising threshold table entries (3D: 4 x 13)
 
 struct BatchJob {
@@ -45,8 +45,6 @@ struct RowGeomHost {
 // (D = 1, 2, 4) when the row fits and the 32-bit spin-1/2 table applies, else
 // 64-lane column windows (D = 0).
 bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out);
-hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,
-                              const BatchWG* wgs, uint32_t nwg, uint32_t colour, hipStream_t s);
 
 // Variant index of a job for the one-launch kernel: kind, dimension and D.
 inline uint32_t batch_class(int kind, int dim, int D)
@@ -55,10 +53,11 @@ inline uint32_t batch_class(int kind, int dim, int D)
     return (uint32_t)kind * 8u + (uint32_t)(dim - 2) * 4u + d;
 }
 
-// All jobs of a half-sweep in one launch (work list sorted by variant).
+// All jobs of a half-sweep in one launch (work list sorted by variant): the
+// call's sweep number `step` runs sweep t + step of every job whose count in
+// this call exceeds step.
 hipError_t launch_batch_all(const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
-                            uint32_t colour, hipStream_t s);
-hipError_t launch_batch_advance(uint32_t* dyn, uint32_t njobs, hipStream_t s);
+                            uint32_t colour, uint32_t step, hipStream_t s);
 hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* out, hipStream_t s);
 
 }  // namespace spinlat

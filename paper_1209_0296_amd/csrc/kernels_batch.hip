@@ -3,16 +3,17 @@
 //
 // Every job keeps its own lattice, threshold table, Philox key, sweep index
 // and record ring; the launch reads them from a device job table.  A work
-// table lists, for one class of jobs (same model kind, dimension and words
-// per lane), the workgroups to run as (job, first item) pairs, so a
+// list names the workgroups to run as (job, first item) pairs, sorted by the
+// job's kernel variant (model kind, dimension, words per lane), so a
 // workgroup only ever touches one job and its reduction goes to that job's
 // record.  Because the random numbers depend on (seed, sweep, site) only, a
 // job's lattice and records are the same alone and in any mix.
 //
-// Per-job counters {t, record slot, sweeps left in this call} live in a
-// small device array that the host uploads before a batch of sweeps; after
-// each sweep k_batch_advance moves them on, so the same sequence of launches
-// serves every sweep and no argument changes between sweeps.
+// Per-job counters {t, record slot, sweeps in this call} live in a small
+// device array that the host uploads once per call; the launches of the
+// call's s-th sweep take s as an argument, so a job runs sweep t + s into
+// record slot + s while s is below its count, and nothing runs between the
+// sweeps to move the counters.
 #include "row_device.hpp"
 #include "stream_device.hpp"
 #include "batch_internal.h"
@@ -25,12 +26,11 @@ namespace {
 
 template <int KIND, int DIM, int D>
 __device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ jobs, const uint32_t* __restrict__ dyn,
-                                                const BatchWG w, uint32_t colour, RowLuts& lut,
-                                                uint32_t (&xch)[2][16][2])
+                                                const BatchWG w, uint32_t colour, uint32_t step,
+                                                RowLuts& lut, uint32_t (&xch)[2][16][2])
 {
     const uint32_t* dj = dyn + kDynWords * w.job;
-    const uint32_t remaining = dj[2];
-    if (remaining == 0) return;  // whole workgroup: this job has no sweep left in this call
+    if (step >= dj[2]) return;  // whole workgroup: this job has no sweep left in this call
     const BatchJob& J = jobs[w.job];
     uint64_t thr_up, thr_down;
     build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
@@ -41,7 +41,7 @@ __device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ job
     a.col[1] = J.col[1];
     a.key0 = J.key0;
     a.key1 = J.key1;
-    a.t = dj[0];
+    a.t = dj[0] + step;
     a.colour = colour;
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
@@ -53,7 +53,7 @@ __device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ job
     half_item<KIND, DIM, D, false>(a, rg, item, ln, lut, xch, thr_up, thr_down, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
-    block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
+    block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
 }
 
 // Jobs whose colour row does not fit one wave (or whose spin-1/2 table has a
@@ -61,10 +61,10 @@ __device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ job
 template <int KIND, int DIM>
 __device__ __forceinline__ void batch_window_body(const BatchJob* __restrict__ jobs,
                                                   const uint32_t* __restrict__ dyn, const BatchWG w,
-                                                  uint32_t colour, streamk::Luts& lut)
+                                                  uint32_t colour, uint32_t step, streamk::Luts& lut)
 {
     const uint32_t* dj = dyn + kDynWords * w.job;
-    if (dj[2] == 0) return;  // whole workgroup: no sweep left for this job
+    if (step >= dj[2]) return;  // whole workgroup: no sweep left for this job
     const BatchJob& J = jobs[w.job];
     uint64_t thr_up, thr_down;
     streamk::build_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
@@ -75,33 +75,14 @@ __device__ __forceinline__ void batch_window_body(const BatchJob* __restrict__ j
     a.col[1] = J.col[1];
     a.key0 = J.key0;
     a.key1 = J.key1;
-    a.t = dj[0];
+    a.t = dj[0] + step;
     a.colour = colour;
     const streamk::StreamGeom sg = *reinterpret_cast<const streamk::StreamGeom*>(J.rg_words);
     streamk::Obs o = {0, 0, 0, 0};
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t item = w.item_base + (threadIdx.x >> 6) * sg.G + lane / sg.W;
     streamk::stream_half_item<KIND, DIM>(a, sg, item, lut, thr_up, thr_down, o);
-    block_accumulate(o.bond, o.mag, o.acc, o.unfl, J.acc + (uint64_t)dj[1] * kSlotWords);
-}
-
-template <int KIND, int DIM, int D>
-__global__ void __launch_bounds__(256) k_batch_half(const BatchJob* __restrict__ jobs,
-                                                    const uint32_t* __restrict__ dyn,
-                                                    const BatchWG* __restrict__ wgs, uint32_t colour)
-{
-    __shared__ RowLuts lut;
-    __shared__ uint32_t xch[2][16][2];
-    batch_half_body<KIND, DIM, D>(jobs, dyn, wgs[blockIdx.x], colour, lut, xch);
-}
-
-template <int KIND, int DIM>
-__global__ void __launch_bounds__(256) k_batch_window(const BatchJob* __restrict__ jobs,
-                                                      const uint32_t* __restrict__ dyn,
-                                                      const BatchWG* __restrict__ wgs, uint32_t colour)
-{
-    __shared__ streamk::Luts lut;
-    batch_window_body<KIND, DIM>(jobs, dyn, wgs[blockIdx.x], colour, lut);
+    block_accumulate(o.bond, o.mag, o.acc, o.unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
 }
 
 // Every job of a half-sweep in one launch: each workgroup runs the variant of
@@ -114,17 +95,19 @@ union BatchLds {
 
 template <int KIND, int DIM>
 __device__ __forceinline__ void dispatch_d(uint32_t d, const BatchJob* jobs, const uint32_t* dyn, const BatchWG w,
-                                           uint32_t colour, BatchLds& lds, uint32_t (&xch)[2][16][2])
+                                           uint32_t colour, uint32_t step, BatchLds& lds,
+                                           uint32_t (&xch)[2][16][2])
 {
-    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, lds.row, xch);
-    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, lds.row, xch);
-    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, lds.row, xch);
-    else batch_window_body<KIND, DIM>(jobs, dyn, w, colour, lds.win);
+    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, step, lds.row, xch);
+    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, step, lds.row, xch);
+    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, step, lds.row, xch);
+    else batch_window_body<KIND, DIM>(jobs, dyn, w, colour, step, lds.win);
 }
 
 __global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ jobs,
                                                    const uint32_t* __restrict__ dyn,
-                                                   const BatchWG* __restrict__ wgs, uint32_t colour)
+                                                   const BatchWG* __restrict__ wgs, uint32_t colour,
+                                                   uint32_t step)
 {
     __shared__ BatchLds lds;
     __shared__ uint32_t xch[2][16][2];
@@ -132,25 +115,13 @@ __global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ 
     const uint32_t cls = jobs[w.job].cls;
     const uint32_t kind = cls >> 3, dim3d = (cls >> 2) & 1u, d = cls & 3u;
     if (kind == KIND_ISING_HALF) {
-        if (dim3d) dispatch_d<KIND_ISING_HALF, 3>(d, jobs, dyn, w, colour, lds, xch);
-        else dispatch_d<KIND_ISING_HALF, 2>(d, jobs, dyn, w, colour, lds, xch);
+        if (dim3d) dispatch_d<KIND_ISING_HALF, 3>(d, jobs, dyn, w, colour, step, lds, xch);
+        else dispatch_d<KIND_ISING_HALF, 2>(d, jobs, dyn, w, colour, step, lds, xch);
     } else if (kind == KIND_ISING_ONE) {
-        if (dim3d) dispatch_d<KIND_ISING_ONE, 3>(d, jobs, dyn, w, colour, lds, xch);
-        else dispatch_d<KIND_ISING_ONE, 2>(d, jobs, dyn, w, colour, lds, xch);
+        if (dim3d) dispatch_d<KIND_ISING_ONE, 3>(d, jobs, dyn, w, colour, step, lds, xch);
+        else dispatch_d<KIND_ISING_ONE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
     } else {
-        dispatch_d<KIND_NE, 2>(d, jobs, dyn, w, colour, lds, xch);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_batch_advance(uint32_t* dyn, uint32_t njobs)
-{
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= njobs) return;
-    uint32_t* d = dyn + kDynWords * j;
-    if (d[2] > 0) {
-        d[0] += 1;  // sweep index
-        d[1] += 1;  // record slot
-        d[2] -= 1;  // sweeps left
+        dispatch_d<KIND_NE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
     }
 }
 
@@ -175,21 +146,6 @@ __global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict_
         o[3] = sum[2];
         o[4] = f.ising ? -1 : sum[3];
     }
-}
-
-template <int KIND, int DIM>
-hipError_t launch_class_d(int D, const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
-                          uint32_t colour, hipStream_t s)
-{
-    if (D == 0)
-        hipLaunchKernelGGL((k_batch_window<KIND, DIM>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
-    else if (D == 4)
-        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 4>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
-    else if (D == 2)
-        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 2>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
-    else
-        hipLaunchKernelGGL((k_batch_half<KIND, DIM, 1>), dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -221,19 +177,6 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out)
     return true;
 }
 
-hipError_t launch_batch_class(int kind, int dim, int D, const BatchJob* jobs, const uint32_t* dyn,
-                              const BatchWG* wgs, uint32_t nwg, uint32_t colour, hipStream_t s)
-{
-    if (nwg == 0) return hipSuccess;
-    if (kind == KIND_NE) return launch_class_d<KIND_NE, 2>(D, jobs, dyn, wgs, nwg, colour, s);
-    if (dim == 2) {
-        if (kind == KIND_ISING_HALF) return launch_class_d<KIND_ISING_HALF, 2>(D, jobs, dyn, wgs, nwg, colour, s);
-        return launch_class_d<KIND_ISING_ONE, 2>(D, jobs, dyn, wgs, nwg, colour, s);
-    }
-    if (kind == KIND_ISING_HALF) return launch_class_d<KIND_ISING_HALF, 3>(D, jobs, dyn, wgs, nwg, colour, s);
-    return launch_class_d<KIND_ISING_ONE, 3>(D, jobs, dyn, wgs, nwg, colour, s);
-}
-
 hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* out, hipStream_t s)
 {
     if (nentries == 0) return hipSuccess;
@@ -242,17 +185,10 @@ hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* o
 }
 
 hipError_t launch_batch_all(const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
-                            uint32_t colour, hipStream_t s)
+                            uint32_t colour, uint32_t step, hipStream_t s)
 {
     if (nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_all, dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_advance(uint32_t* dyn, uint32_t njobs, hipStream_t s)
-{
-    if (njobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_advance, dim3((njobs + 255) / 256), dim3(256), 0, s, dyn, njobs);
+    hipLaunchKernelGGL(k_batch_all, dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour, step);
     return hipGetLastError();
 }
 
