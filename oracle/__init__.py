@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 ISING = 0
 NORTH_EAST = 1
 NE_TILES = 2  # North-East model, the paper's random sub-lattice algorithm
+NE_BALANCED = 3  # its balanced variant (red, then white sites; four launches per sweep)
 INIT_COLD = 0
 INIT_RANDOM = 1
 RECORD_WORDS = 5  # t, bond_sum, mag, accepted, unflipped
@@ -95,6 +96,8 @@ def lib():
         L.or_run.restype = ctypes.c_int
         L.or_ne_tiles_launch.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
         L.or_ne_tiles_launch.restype = ctypes.c_int64
+        L.or_ne_balanced_launch.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+        L.or_ne_balanced_launch.restype = ctypes.c_int64
         L.or_threshold_table.argtypes = [P, ctypes.c_void_p, ctypes.c_int64]
         L.or_threshold_table.restype = ctypes.c_int64
         _lib = L
@@ -212,6 +215,17 @@ def ne_tiles_launch(p: Params, src: np.ndarray, launch: int):
     ps = p.c_struct()
     assert src.dtype == np.int8 and src.flags.c_contiguous and src.size == p.nsites
     acc = lib().or_ne_tiles_launch(ctypes.byref(ps), src.ctypes.data, dst.ctypes.data, launch)
+    if acc < 0:
+        raise ValueError("invalid sub-lattice parameters")
+    return dst, int(acc)
+
+
+def ne_balanced_launch(p: Params, src: np.ndarray, launch: int):
+    """One launch of the balanced NE variant: returns (new lattice, accepted)."""
+    dst = np.empty_like(src)
+    ps = p.c_struct()
+    assert src.dtype == np.int8 and src.flags.c_contiguous and src.size == p.nsites
+    acc = lib().or_ne_balanced_launch(ctypes.byref(ps), src.ctypes.data, dst.ctypes.data, launch)
     if acc < 0:
         raise ValueError("invalid sub-lattice parameters")
     return dst, int(acc)

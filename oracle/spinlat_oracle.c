@@ -23,7 +23,8 @@
  *     up-density c (excitation energy 1, c = 1/(1+e^{1/T})).
  *   - Sec. 3.2, the NE algorithm with random sub-lattices: square sub-lattices,
  *     lambda random sites per iteration, two launches per sweep
- *     (or_ne_tiles_launch below, with its readings).
+ *     (or_ne_tiles_launch below, with its readings), and its balanced variant
+ *     that alternates the two colours (or_ne_balanced_launch).
  *
  * Readings of points the paper leaves open (all documented in the design
  * notes of the repository):
@@ -410,6 +411,83 @@ int64_t or_ne_tiles_launch(const or_params* p, const int8_t* src, int8_t* dst, u
 }
 
 /* ---------------------------------------------------------------------- */
+/* The balanced variant of the sub-lattice NE algorithm (end of Sec. 3.2): an
+ * iteration updates lambda random sites of colour 0 ("red") of the
+ * sub-lattice, then lambda random sites of colour 1 ("white"); four launches
+ * make a sweep, each with q' = P/(8 lambda) iterations, so a sub-lattice gets P
+ * attempts per sweep.
+ *
+ * Readings: boundaries as in or_ne_tiles_launch (other sub-lattices as at the
+ * start of the launch, the own sub-lattice live).  Sites of one colour are
+ * never neighbours, so the lambda updates of a half-iteration see frozen
+ * neighbours.  When several attempts of a half-iteration draw the same site,
+ * only the lowest-numbered one is applied: each site then gets at most one
+ * Metropolis move per half-iteration, a composition of moves that each keep
+ * the product measure stationary.  Random numbers: attempt
+ * a = (2 j + h) lambda + l (thread l, iteration j, half h = 0 red, 1 white)
+ * uses words 2 (a mod 2) and 2 (a mod 2) + 1 of Philox4x32-10(key = seed,
+ * ctr = (tau, a/2, launch, 3)); the first picks the site
+ * floor(word (P/2) / 2^32) among the P/2 sites of colour h, numbered row by
+ * row (row r holds the columns 2i + ((r + h) mod 2)); the second decides
+ * acceptance.  `accepted` counts flips.  Sweep t uses launches 4t .. 4t+3. */
+
+int64_t or_ne_balanced_launch(const or_params* p, const int8_t* src, int8_t* dst, uint32_t launch)
+{
+    const int L = p->L, B = p->tile, lam = p->lambda;
+    if (p->dim != 2 || B < 2 || (B & 1) || lam < 1 || L % B != 0 || (B * B) % (8 * lam) != 0)
+        return -1;
+    const int P = B * B, half_sites = P / 2, tiles_x = L / B, q = P / (8 * lam);
+    const uint64_t thr_up = or_threshold_from_prob(p->c / (1.0 - p->c));
+    const uint64_t thr_down = or_threshold_from_prob((1.0 - p->c) / p->c);
+    memcpy(dst, src, (size_t)L * L);
+    int64_t accepted = 0;
+#pragma omp parallel for schedule(static) reduction(+ : accepted)
+    for (int tau = 0; tau < tiles_x * tiles_x; ++tau) {
+        const int x0 = (tau % tiles_x) * B, y0 = (tau / tiles_x) * B;
+        int8_t* tile = (int8_t*)malloc((size_t)P);
+        char* claimed = (char*)malloc((size_t)half_sites);
+        for (int r = 0; r < B; ++r)
+            for (int cc = 0; cc < B; ++cc) tile[r * B + cc] = src[idx3(L, x0 + cc, y0 + r, 0)];
+        for (int j = 0; j < q; ++j)
+            for (int h = 0; h < 2; ++h) {
+                memset(claimed, 0, (size_t)half_sites);
+                for (int l = 0; l < lam; ++l) {
+                    const uint32_t a = (uint32_t)((2 * j + h) * lam + l);
+                    uint32_t ctr[4] = {(uint32_t)tau, a / 2, launch, OR_TAG_NE_BALANCED};
+                    uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+                    uint32_t w[4];
+                    or_philox4x32_10(ctr, key, w);
+                    const int i = (int)(((uint64_t)w[(a % 2) * 2] * (uint64_t)half_sites) >> 32);
+                    if (claimed[i]) continue;       /* a lower-numbered attempt has it */
+                    claimed[i] = 1;
+                    const int r = i / (B / 2);
+                    const int cc = 2 * (i % (B / 2)) + ((r + h) & 1);
+                    const int s = r * B + cc;
+                    const int n = tile[s] & 1;
+                    int north, east;
+                    if (r > 0) north = tile[(r - 1) * B + cc] & 1;
+                    else if (tiles_x == 1) north = tile[(B - 1) * B + cc] & 1;
+                    else north = src[idx3(L, x0 + cc, wrap(y0 - 1, L), 0)] & 1;
+                    if (cc < B - 1) east = tile[r * B + cc + 1] & 1;
+                    else if (tiles_x == 1) east = tile[r * B] & 1;
+                    else east = src[idx3(L, wrap(x0 + B, L), y0 + r, 0)] & 1;
+                    if (!(north && east)) continue;
+                    const uint64_t thr = n ? thr_down : thr_up;
+                    if ((uint64_t)w[(a % 2) * 2 + 1] < thr) {
+                        tile[s] = (int8_t)((n ^ 1) | 2);
+                        accepted += 1;
+                    }
+                }
+            }
+        for (int r = 0; r < B; ++r)
+            for (int cc = 0; cc < B; ++cc) dst[idx3(L, x0 + cc, y0 + r, 0)] = tile[r * B + cc];
+        free(tile);
+        free(claimed);
+    }
+    return accepted;
+}
+
+/* ---------------------------------------------------------------------- */
 /* A run of n sweeps starting at sweep index t0.  Sweep t updates colour 0
  * then colour 1 (Alg. I steps 5-7: two launches per Monte Carlo step).  After
  * sweep t the record r = {t+1, bond_sum, mag, accepted, unflipped} is
@@ -424,14 +502,26 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
     (void)nthreads;
 #endif
     int8_t* tmp = NULL;
-    if (p->model == OR_NE_TILES) {
+    if (p->model == OR_NE_TILES || p->model == OR_NE_BALANCED) {
         tmp = (int8_t*)malloc((size_t)p->L * p->L);
         if (!tmp) return -1;
     }
     for (uint32_t n = 0; n < nsweeps; ++n) {
         uint32_t t = t0 + n;
         int64_t acc = 0;
-        if (p->model == OR_NE_TILES) {
+        if (p->model == OR_NE_BALANCED) {
+            int64_t a4 = 0;
+            for (uint32_t i = 0; i < 4; ++i) {
+                const int64_t ai = or_ne_balanced_launch(p, (i & 1) ? tmp : s, (i & 1) ? s : tmp,
+                                                         4 * t + i);
+                if (ai < 0) {
+                    free(tmp);
+                    return -1;
+                }
+                a4 += ai;
+            }
+            acc = a4;
+        } else if (p->model == OR_NE_TILES) {
             const int64_t a0 = or_ne_tiles_launch(p, s, tmp, 2 * t);
             const int64_t a1 = a0 < 0 ? -1 : or_ne_tiles_launch(p, tmp, s, 2 * t + 1);
             if (a1 < 0) {

@@ -16,15 +16,17 @@ extern "C" {
 #define OR_ISING 0
 #define OR_NORTH_EAST 1
 #define OR_NE_TILES 2   /* North-East model, paper's random sub-lattice algorithm */
+#define OR_NE_BALANCED 3 /* its balanced variant: red, then white sites */
 #define OR_INIT_COLD 0
 #define OR_INIT_RANDOM 1
 #define OR_TAG_SWEEP 0u
 #define OR_TAG_INIT 1u
 #define OR_TAG_NE_TILES 2u
+#define OR_TAG_NE_BALANCED 3u
 #define OR_RECORD_WORDS 5
 
 typedef struct {
-    int32_t model;   /* OR_ISING, OR_NORTH_EAST or OR_NE_TILES */
+    int32_t model;   /* OR_ISING, OR_NORTH_EAST, OR_NE_TILES or OR_NE_BALANCED */
     int32_t dim;     /* 2 or 3 (NE: 2) */
     int32_t L;       /* even */
     int32_t two_s;   /* 1: s in {-1,+1}; 2: s in {-1,0,+1} */
@@ -52,6 +54,7 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
            int64_t* records, int nthreads);
 int64_t or_threshold_table(const or_params* p, uint64_t* out, int64_t cap);
 int64_t or_ne_tiles_launch(const or_params* p, const int8_t* src, int8_t* dst, uint32_t launch);
+int64_t or_ne_balanced_launch(const or_params* p, const int8_t* src, int8_t* dst, uint32_t launch);
 int or_abi(void);
 
 #ifdef __cplusplus

@@ -207,3 +207,120 @@ def test_invalid_parameters_rejected(L, B, lam):
     s = np.zeros((L, L), dtype=np.int8)
     with pytest.raises(ValueError):
         O.ne_tiles_launch(p, s, 0)
+
+
+# ---------------------------------------------------------------------------
+# Balanced variant (end of Sec. 3.2): red then white sites, four launches per sweep.
+
+TAG_NE_BALANCED = 3
+
+
+def _bparams(L, B, lam, c, seed=1):
+    return O.Params(model=O.NE_BALANCED, dim=2, L=L, c=c, seed=seed, tile=B, lam=lam)
+
+
+def _predict_balanced_one_iteration(p, src, launch):
+    """lambda = P/8: one iteration per launch; the red half reads src, the white
+    half reads its own sub-lattice after the red half and the other
+    sub-lattices as in src; lowest-numbered attempt wins."""
+    L, B = p.L, p.tile
+    P, lam = B * B, p.lam
+    up_thr = O.threshold_from_prob(p.c / (1 - p.c))
+    down_thr = O.threshold_from_prob((1 - p.c) / p.c)
+    one = L == B
+    cur = src.copy()
+    flips = 0
+    for h in range(2):
+        n = cur & 1
+        n0 = src & 1
+        # neighbour inside the own sub-lattice (or B = L): current; else launch start
+        north = np.where((np.arange(L) % B != 0)[:, None] | one, np.roll(n, 1, axis=0),
+                         np.roll(n0, 1, axis=0))
+        east = np.where((np.arange(L) % B != B - 1)[None, :] | one, np.roll(n, -1, axis=1),
+                        np.roll(n0, -1, axis=1))
+        nxt = cur.copy()
+        for tau in range((L // B) ** 2):
+            x0, y0 = (tau % (L // B)) * B, (tau // (L // B)) * B
+            seen = set()
+            for l in range(lam):
+                a = h * lam + l
+                w = O.philox4x32_10([tau, a // 2, launch, TAG_NE_BALANCED],
+                                    [p.seed & 0xFFFFFFFF, p.seed >> 32])
+                i = (w[2 * (a % 2)] * (P // 2)) >> 32
+                if i in seen:
+                    continue
+                seen.add(i)
+                r = i // (B // 2)
+                cc = 2 * (i % (B // 2)) + ((r + h) & 1)
+                y, x = y0 + r, x0 + cc
+                assert (x + y) % 2 == h
+                if not (north[y, x] and east[y, x]):
+                    continue
+                thr = down_thr if n[y, x] else up_thr
+                if w[2 * (a % 2) + 1] < thr:
+                    nxt[y, x] = ((cur[y, x] & 1) ^ 1) | 2
+                    flips += 1
+        cur = nxt
+    return cur, flips
+
+
+@pytest.mark.parametrize("L,B,c,launch", [(16, 8, 0.3, 5), (16, 4, 0.6, 0), (24, 8, 0.45, 77)])
+def test_balanced_one_iteration_predicted_site_by_site(L, B, c, launch):
+    p = _bparams(L, B, (B * B) // 8, c, seed=13)
+    src = _random_state(L, 0.8, seed=L * B)
+    dst, acc = O.ne_balanced_launch(p, src, launch)
+    want, want_acc = _predict_balanced_one_iteration(p, src, launch)
+    np.testing.assert_array_equal(dst, want)
+    assert acc == want_acc
+
+
+def test_balanced_keeps_the_product_measure():
+    """Start from exact samples of Bernoulli(c)^N and apply one sweep (four
+    launches): the up density and the north/east pair density stay c and c^2
+    (the variant keeps the measure stationary), within 5 standard errors."""
+    c, L = 0.42, 32
+    dens, pairs = [], []
+    for seed in range(40):
+        p = _bparams(L, 8, 2, c, seed=1000 + seed)
+        rng = np.random.default_rng(seed)
+        s = np.ascontiguousarray((rng.random((L, L)) < c).astype(np.int8))
+        O.run(p, s, seed, 1)
+        n = s & 1
+        dens.append(n.mean())
+        pairs.append((n * np.roll(n, 1, axis=0)).mean() + (n * np.roll(n, -1, axis=1)).mean())
+    N = L * L * len(dens)
+    assert abs(np.mean(dens) - c) < 5 * math.sqrt(c * (1 - c) / N)
+    assert abs(np.mean(pairs) / 2 - c * c) < 5 * math.sqrt(c * c * (1 - c * c) / N)
+
+
+def test_balanced_launch_invariants_and_sweep():
+    L, B, lam = 32, 8, 4
+    p = _bparams(L, B, lam, 0.4, seed=43)
+    src = _random_state(L, 0.6, seed=7)
+    dst, acc = O.ne_balanced_launch(p, src, 9)
+    changed = (dst & 1) != (src & 1)
+    assert acc >= changed.sum() and (acc - changed.sum()) % 2 == 0
+    assert np.all(dst[changed] & 2) and np.all((dst & 2) >= (src & 2))
+    zero = np.zeros((L, L), dtype=np.int8)
+    dz, az = O.ne_balanced_launch(p, zero, 9)
+    assert az == 0 and not dz.any()
+    # a sweep is launches 4t .. 4t+3, alternating the two copies
+    s = O.init_lattice(p)
+    cur, tot = s.copy(), 0
+    for i in range(4):
+        cur, a = O.ne_balanced_launch(p, cur, 4 * 5 + i)
+        tot += a
+    s2 = s.copy()
+    rec = O.run(p, s2, 5, 1)
+    np.testing.assert_array_equal(s2, cur)
+    assert rec[0, 3] == tot and rec[0, 0] == 6
+    # the balanced and the plain variant draw from different streams
+    q = _params(L, B, lam, 0.4, seed=43)
+    assert not np.array_equal(O.ne_tiles_launch(q, src, 9)[0], dst)
+
+
+@pytest.mark.parametrize("L,B,lam", [(32, 8, 16), (32, 8, 3), (30, 10, 1)])
+def test_balanced_invalid_parameters_rejected(L, B, lam):
+    p = _bparams(L, B, lam, 0.3)
+    with pytest.raises(ValueError):
+        O.ne_balanced_launch(p, np.zeros((L, L), dtype=np.int8), 0)
