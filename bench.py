@@ -88,9 +88,9 @@ def time_workload(S, torch, name, cfg, steps, warmup, T=None):
     mode = lat.get_launch()
     lat.close()
     attempts = p.nsites * steps
-    if p.model == S.NE_SUBLATTICE:
-        # two launches per sweep, each reading and writing the whole lattice
-        launches_per_sweep = 2
+    if p.model in (S.NE_SUBLATTICE, S.NE_SUBLATTICE_BALANCED):
+        # two (balanced: four) launches per sweep, each reading and writing the lattice
+        launches_per_sweep = 2 if p.model == S.NE_SUBLATTICE else 4
         bytes_per_launch = 2 * p.nsites
     else:
         launches_per_sweep = 1 if mode[0] == S.MODE_FUSED else 2
@@ -214,7 +214,8 @@ def main():
           f"{main_res['ms_per_step']:.4f} ms/sweep", file=sys.stderr, flush=True)
     secondary = []
     if not args.no_secondary:
-        for key in ("ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096", "ne2d_sub_L4096"):
+        for key in ("ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096", "ne2d_sub_L4096",
+                    "ne2d_subbal_L4096"):
             r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)

@@ -23,7 +23,11 @@
  *     neighbours in the same sub-lattice as at the start of the iteration; an
  *     accepted move sets n to 1-n, so a site drawn twice in one iteration
  *     flips once.  With B = L and lambda = 1 (not offered by the kernels) this
- *     would be the serial random-site algorithm.
+ *     would be the serial random-site algorithm.  The balanced variant
+ *     (SL_NE_SUBLATTICE_BALANCED, end of Sec. 3.2) draws lambda sites of colour
+ *     0, then lambda of colour 1 per iteration, P/(8 lambda) iterations per
+ *     launch, four launches per sweep; when attempts of a half draw the same
+ *     site only the lowest-numbered one is applied.
  *
  * Random-number contract (result is a pure function of seed, sweep and site,
  * so any launch schedule gives the same lattice bit for bit):
@@ -41,6 +45,11 @@
  *   words 2(a mod 2) and 2(a mod 2)+1 of Philox4x32-10(key = seed,
  *   ctr = (tau, a/2, m, 2)): the first picks the site floor(word B^2 / 2^32)
  *   (row-major in the sub-lattice), the second is compared with the threshold.
+ *   Balanced variant: attempt a = (2j + h)*lambda + l (half h: colour h) in
+ *   launch m (4t .. 4t+3) uses words 2(a mod 2), 2(a mod 2)+1 of
+ *   Philox4x32-10(key = seed, ctr = (tau, a/2, m, 3)): the first picks the site
+ *   floor(word (B^2/2) / 2^32) among the sites of colour h, row by row (row r
+ *   holds columns 2i + ((r + h) mod 2)), the second decides acceptance.
  *   Initial state: word(seed, 1, 0, colour, k, 1, 0): spin-1/2 +1 iff
  *   < 2^31; spin-1 floor(3 word / 2^32) - 1; NE up iff < floor(c 2^32).
  *   Threshold: thr(dE) = 2^32 if dE <= 0, else floor(exp(-dE/T) 2^32), with
@@ -82,13 +91,16 @@ typedef enum sl_status {
     SL_E_BUFFER = 3,      /* caller buffer too small, misaligned or NULL */
     SL_E_HIP = 4,         /* a HIP runtime call failed (message has its text) */
     SL_E_STATE = 5,       /* call not allowed now (record ring full, ...) */
-    SL_E_OVERFLOW = 6     /* sweep index would reach 2^32 (NE sub-lattices: 2^31) */
+    SL_E_OVERFLOW = 6     /* sweep index would reach 2^32 (NE sub-lattices: 2^31,
+                             balanced: 2^30) */
 } sl_status;
 
 typedef enum sl_model {
     SL_ISING = 0,
     SL_NORTH_EAST = 1,    /* NE model, checkerboard half-sweeps */
-    SL_NE_SUBLATTICE = 2  /* NE model, random sub-lattice algorithm (Sec. 3.2) */
+    SL_NE_SUBLATTICE = 2, /* NE model, random sub-lattice algorithm (Sec. 3.2) */
+    SL_NE_SUBLATTICE_BALANCED = 3 /* its balanced variant: colour 0 then colour 1 sites
+                                     per iteration, four launches per sweep */
 } sl_model;
 
 typedef enum sl_init {
@@ -111,10 +123,11 @@ typedef struct sl_params {
     uint64_t record_capacity; /* records held on the device between sl_measure calls, >= 1 */
     const int8_t* init_spins; /* SL_INIT_BUFFER: device pointer to L^dim bytes in natural
                                  row-major order [z][y][x] (Ising: s; NE: n | flag<<1) */
-    int32_t ne_side;          /* SL_NE_SUBLATTICE: sub-lattice side B in {8,16,32,64},
-                                 L % B == 0 (ignored by the other models) */
-    int32_t ne_lambda;        /* SL_NE_SUBLATTICE: sites updated together, a power of two
-                                 in [2, 128] with 2 lambda <= B^2 (ignored otherwise) */
+    int32_t ne_side;          /* SL_NE_SUBLATTICE[_BALANCED]: sub-lattice side B in
+                                 {8,16,32,64}, L % B == 0 (ignored by the other models) */
+    int32_t ne_lambda;        /* SL_NE_SUBLATTICE[_BALANCED]: sites updated together, a power
+                                 of two in [2, 128] with 2 lambda <= B^2 (balanced:
+                                 8 lambda <= B^2); ignored otherwise */
 } sl_params;
 
 typedef struct sl_record {

@@ -193,7 +193,7 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     p->record_capacity = cfg->record_capacity;
     sl_status st = validate(p);
     if (st != SL_OK) return st;
-    if (p->model == SL_NE_SUBLATTICE)
+    if (is_sub_lattice(p->model))
         return fail(SL_E_UNSUPPORTED, "batched jobs use the checkerboard sweep; the NE "
                                       "sub-lattice algorithm runs as a single lattice");
     *foot = job_foot(p, cfg->record_capacity);

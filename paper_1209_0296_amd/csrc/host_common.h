@@ -28,6 +28,8 @@ const char* last_error();
 sl_status fail(sl_status st, const char* fmt, ...);
 sl_status hip_fail(hipError_t e, const char* what);
 int kind_of(const sl_params* p);
+bool is_sub_lattice(int model);  // SL_NE_SUBLATTICE or its balanced variant
+uint64_t sweep_limit(int model);  // sweep indices stay below this
 sl_status validate(const sl_params* p);  // full validation of a lattice's parameters
 Layout layout_of(const sl_params* p);
 uint64_t thr_from_prob(double pr);

@@ -52,6 +52,7 @@ namespace {
 
 constexpr int kLdsBudget = 32768;  // bytes of LDS per one-wavefront workgroup
 constexpr uint32_t kTagNeSub = 2u;
+constexpr uint32_t kTagNeBal = 3u;
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
@@ -166,17 +167,109 @@ __device__ __forceinline__ void site_offsets(uint32_t site, uint32_t& own, uint3
     }
 }
 
-template <int B, int LPT, bool WRAP>
-__global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
+// Copy sub-lattice tau with its north row and east column from the colour
+// arrays into LDS (natural order, see SubLayout); lanes l of LPT share it.
+template <int B, int LPT>
+__device__ __forceinline__ void load_tile(const NeSubArgs& a, uint8_t* t, uint32_t l, uint32_t x0,
+                                          uint32_t y0)
 {
     using Lay = SubLayout<B>;
     constexpr int S = Lay::stride;
     constexpr int UNIT = Lay::unit;
+    constexpr int NU = (B + 1) * Lay::units_per_row;  // colour-vector pairs
+    const uint32_t ynorth = y0 == 0 ? a.L - 1 : y0 - 1;
+    const size_t kx = x0 >> 1;
+    // north row and sub-lattice rows: both colours, interleaved
+#pragma unroll
+    for (int i = 0; i < (NU + LPT - 1) / LPT; ++i) {
+        const int u = (int)l + i * LPT;
+        if (u < NU) {
+            const int pr = u / Lay::units_per_row, part = u % Lay::units_per_row;
+            const uint32_t y = pr == 0 ? ynorth : y0 + pr - 1;
+            const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
+            const ColourVec<UNIT> c0 = load_vec<UNIT>(a.src[0] + off);
+            const ColourVec<UNIT> c1 = load_vec<UNIT>(a.src[1] + off);
+            const bool odd = (y & 1u) != 0;  // colour 1 holds the even x of odd rows
+            uint2* dstp = reinterpret_cast<uint2*>(t + pr * S + part * 2 * UNIT);
+#pragma unroll
+            for (int k = 0; k < UNIT / 4; ++k)
+                dstp[k] = odd ? interleave(c1.w[k], c0.w[k]) : interleave(c0.w[k], c1.w[k]);
+        }
+    }
+    // east column: site (x0 + B, y) has colour (x0 + B + y) & 1
+    const uint32_t xe = x0 + B == a.L ? 0u : x0 + B;
+#pragma unroll
+    for (int i = 0; i < (B + LPT - 1) / LPT; ++i) {
+        const int r = (int)l + i * LPT;
+        if (r < B) {
+            const uint32_t y = y0 + r;
+            t[(r + 1) * S + B] = a.src[(xe + y) & 1u][(size_t)y * a.Lh + (xe >> 1)];
+        }
+    }
+}
+
+// The sub-lattice rows back to the colour arrays of the destination copy.
+template <int B, int LPT>
+__device__ __forceinline__ void store_tile(const NeSubArgs& a, const uint8_t* t, uint32_t l,
+                                           uint32_t x0, uint32_t y0)
+{
+    using Lay = SubLayout<B>;
+    constexpr int S = Lay::stride;
+    constexpr int UNIT = Lay::unit;
+    constexpr int NW = B * Lay::units_per_row;
+    const size_t kx = x0 >> 1;
+#pragma unroll
+    for (int i = 0; i < (NW + LPT - 1) / LPT; ++i) {
+        const int u = (int)l + i * LPT;
+        if (u < NW) {
+            const int r = u / Lay::units_per_row, part = u % Lay::units_per_row;
+            const uint32_t y = y0 + r;
+            const uint2* srcp = reinterpret_cast<const uint2*>(t + (r + 1) * S + part * 2 * UNIT);
+            ColourVec<UNIT> c0, c1;
+            const bool odd = (y & 1u) != 0;
+#pragma unroll
+            for (int k = 0; k < UNIT / 4; ++k) {
+                uint32_t e, o;
+                split(srcp[k], e, o);
+                c0.w[k] = odd ? o : e;
+                c1.w[k] = odd ? e : o;
+            }
+            const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
+            store_vec<UNIT>(a.dst[0] + off, c0);
+            store_vec<UNIT>(a.dst[1] + off, c1);
+        }
+    }
+}
+
+// Wavefront sums of the per-lane counts into the records.
+__device__ __forceinline__ void add_counts(const NeSubArgs& a, uint32_t lane, int changed, int mag,
+                                           int bond, int fresh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) changed += __shfl_xor(changed, off, 64);
+    if (lane == 0 && changed != 0)
+        atomicAdd(&a.acc[(blockIdx.x % kSub) * kQ + 2], (unsigned long long)changed);
+    if (a.obs) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mag += __shfl_xor(mag, off, 64);
+            bond += __shfl_xor(bond, off, 64);
+            fresh += __shfl_xor(fresh, off, 64);
+        }
+        unsigned long long* o = a.obs + (blockIdx.x % kSub) * kQ;
+        if (lane == 0 && bond != 0) atomicAdd(&o[0], (unsigned long long)bond);
+        if (lane == 1 && mag != 0) atomicAdd(&o[1], (unsigned long long)mag);
+        if (lane == 2 && fresh != 0) atomicAdd(&o[3], (unsigned long long)fresh);
+    }
+}
+
+template <int B, int LPT, bool WRAP>
+__global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
+{
+    using Lay = SubLayout<B>;
     constexpr int TPW = tiles_per_wave<B, LPT>();
     constexpr int LOGB = ilog2(B);
     constexpr int QIT = B * B / (4 * LPT);  // q = P / (2 lambda), lambda = 2 LPT
-    constexpr int NU = (B + 1) * Lay::units_per_row;  // colour-vector pairs per load
-    constexpr int NW = B * Lay::units_per_row;        // colour-vector pairs per store
     __shared__ __align__(16) uint8_t lds[TPW * Lay::bytes];
 
     const uint32_t lane = threadIdx.x;
@@ -188,36 +281,7 @@ __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
         uint8_t* t = lds + g * Lay::bytes;
         const uint32_t tx = tau % a.tiles_x, ty = tau / a.tiles_x;
         const uint32_t x0 = tx * B, y0 = ty * B;
-        const uint32_t ynorth = y0 == 0 ? a.L - 1 : y0 - 1;
-        const size_t kx = x0 >> 1;
-
-        // north row and sub-lattice rows: both colours, interleaved
-#pragma unroll
-        for (int i = 0; i < (NU + LPT - 1) / LPT; ++i) {
-            const int u = (int)l + i * LPT;
-            if (u < NU) {
-                const int pr = u / Lay::units_per_row, part = u % Lay::units_per_row;
-                const uint32_t y = pr == 0 ? ynorth : y0 + pr - 1;
-                const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
-                const ColourVec<UNIT> c0 = load_vec<UNIT>(a.src[0] + off);
-                const ColourVec<UNIT> c1 = load_vec<UNIT>(a.src[1] + off);
-                const bool odd = (y & 1u) != 0;  // colour 1 holds the even x of odd rows
-                uint2* dstp = reinterpret_cast<uint2*>(t + pr * S + part * 2 * UNIT);
-#pragma unroll
-                for (int k = 0; k < UNIT / 4; ++k)
-                    dstp[k] = odd ? interleave(c1.w[k], c0.w[k]) : interleave(c0.w[k], c1.w[k]);
-            }
-        }
-        // east column: site (x0 + B, y) has colour (x0 + B + y) & 1
-        const uint32_t xe = x0 + B == a.L ? 0u : x0 + B;
-#pragma unroll
-        for (int i = 0; i < (B + LPT - 1) / LPT; ++i) {
-            const int r = (int)l + i * LPT;
-            if (r < B) {
-                const uint32_t y = y0 + r;
-                t[(r + 1) * S + B] = a.src[(xe + y) & 1u][(size_t)y * a.Lh + (xe >> 1)];
-            }
-        }
+        load_tile<B, LPT>(a, t, l, x0, y0);
 
         if (a.obs) observe_tile<B, LPT>(t, l, mag, bond, fresh);
 
@@ -273,50 +337,116 @@ __global__ void __launch_bounds__(64) k_ne_sub(NeSubArgs a)
             }
         }
 
-        // the sub-lattice rows back to HBM, split into colours
-#pragma unroll
-        for (int i = 0; i < (NW + LPT - 1) / LPT; ++i) {
-            const int u = (int)l + i * LPT;
-            if (u < NW) {
-                const int r = u / Lay::units_per_row, part = u % Lay::units_per_row;
-                const uint32_t y = y0 + r;
-                const uint2* srcp = reinterpret_cast<const uint2*>(t + (r + 1) * S + part * 2 * UNIT);
-                ColourVec<UNIT> c0, c1;
-                const bool odd = (y & 1u) != 0;
-#pragma unroll
-                for (int k = 0; k < UNIT / 4; ++k) {
-                    uint32_t e, o;
-                    split(srcp[k], e, o);
-                    c0.w[k] = odd ? o : e;
-                    c1.w[k] = odd ? e : o;
-                }
-                const size_t off = (size_t)y * a.Lh + kx + part * UNIT;
-                store_vec<UNIT>(a.dst[0] + off, c0);
-                store_vec<UNIT>(a.dst[1] + off, c1);
-            }
-        }
+        store_tile<B, LPT>(a, t, l, x0, y0);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) changed += __shfl_xor(changed, off, 64);
-    if (lane == 0 && changed != 0)
-        atomicAdd(&a.acc[(blockIdx.x % kSub) * kQ + 2], (unsigned long long)changed);
-    if (a.obs) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            mag += __shfl_xor(mag, off, 64);
-            bond += __shfl_xor(bond, off, 64);
-            fresh += __shfl_xor(fresh, off, 64);
-        }
-        unsigned long long* o = a.obs + (blockIdx.x % kSub) * kQ;
-        if (lane == 0 && bond != 0) atomicAdd(&o[0], (unsigned long long)bond);
-        if (lane == 1 && mag != 0) atomicAdd(&o[1], (unsigned long long)mag);
-        if (lane == 2 && fresh != 0) atomicAdd(&o[3], (unsigned long long)fresh);
-    }
+    add_counts(a, lane, changed, mag, bond, fresh);
+}
+
+// Balanced variant: each iteration draws lambda sites of colour 0, then lambda
+// sites of colour 1 (half h); P/(8 lambda) iterations per launch, four
+// launches per sweep.  Sites of one colour are not neighbours, so the
+// attempts of a half only read frozen neighbours; when attempts of a half
+// draw the same site only the lowest-numbered one applies.  Each sub-lattice
+// keeps an owner word per site of the half's colour: attempts post their
+// number with an LDS atomic minimum, read it back, and only the owner
+// evaluates the move and resets the word.  The winner's site is unique, so
+// its store needs no atomic.
+template <int B, int LPT>
+constexpr int bal_tile_bytes()
+{
+    return SubLayout<B>::bytes + 4 * (B * B / 2);
 }
 
 template <int B, int LPT>
-hipError_t launch_one(const NeSubArgs& a, hipStream_t s)
+constexpr int bal_tiles_per_wave()
 {
+    return (64 / LPT) < (kLdsBudget / bal_tile_bytes<B, LPT>()) ? (64 / LPT)
+                                                                : (kLdsBudget / bal_tile_bytes<B, LPT>());
+}
+
+template <int B, int LPT, bool WRAP>
+__global__ void __launch_bounds__(64) k_ne_bal(NeSubArgs a)
+{
+    using Lay = SubLayout<B>;
+    constexpr int TB = bal_tile_bytes<B, LPT>();
+    constexpr int TPW = bal_tiles_per_wave<B, LPT>();
+    constexpr int HS = B * B / 2;  // sites of one colour
+    constexpr int LOGHS = ilog2(HS), LOGBH = ilog2(B / 2);
+    constexpr int QIT = B * B / (16 * LPT);  // P / (8 lambda), lambda = 2 LPT
+    static_assert(Lay::bytes % 4 == 0, "owner words must be aligned");
+    __shared__ __align__(16) uint8_t lds[TPW * TB];
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t g = lane / LPT;
+    const uint32_t l = lane % LPT;
+    const uint32_t tau = blockIdx.x * TPW + g;
+    int changed = 0, mag = 0, bond = 0, fresh = 0;
+    if (g < (uint32_t)TPW && tau < a.ntiles) {
+        uint8_t* t = lds + g * TB;
+        uint32_t* owner = reinterpret_cast<uint32_t*>(t + Lay::bytes);
+        const uint32_t x0 = (tau % a.tiles_x) * B, y0 = (tau / a.tiles_x) * B;
+        load_tile<B, LPT>(a, t, l, x0, y0);
+        for (int i = (int)l; i < HS; i += LPT) owner[i] = 0xFFFFFFFFu;
+        if (a.obs) observe_tile<B, LPT>(t, l, mag, bond, fresh);
+
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        for (int j = 0; j < QIT; ++j) {
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h) {
+                const Words4 w =
+                    philox4x32_10(tau, (2u * j + h) * LPT + l, a.launch, kTagNeBal, ks);
+                uint32_t idx[2], own[2], vs[2], vn[2], ve[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    idx[m] = w.w[2 * m] >> (32 - LOGHS);  // floor(word (P/2) / 2^32)
+                    const uint32_t r = idx[m] >> LOGBH;
+                    const uint32_t cc = 2u * (idx[m] & (B / 2 - 1)) + ((r + h) & 1u);
+                    uint32_t north, east;
+                    site_offsets<B, WRAP>((r << ilog2(B)) + cc, own[m], north, east);
+                    vs[m] = t[own[m]];
+                    vn[m] = t[north];
+                    ve[m] = t[east];
+                    atomicMin(owner + idx[m], 2u * l + (uint32_t)m);
+                }
+                uint32_t win[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    win[m] = __hip_atomic_load(owner + idx[m], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP) == 2u * l + (uint32_t)m;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const uint32_t n = vs[m] & 1u;
+                    const uint32_t allow = vn[m] & ve[m] & 1u;
+                    const uint32_t thr_m1 = n ? a.thr_m1_down : a.thr_m1_up;
+                    const uint32_t never = (a.never >> n) & 1u;
+                    const bool ok = (win[m] & allow & (w.w[2 * m + 1] <= thr_m1 ? 1u : 0u) &
+                                     (never ^ 1u)) != 0u;
+                    if (ok) {
+                        t[own[m]] = (uint8_t)((n ^ 1u) | 2u);
+                        changed += 1;
+                    }
+                    if (win[m]) owner[idx[m]] = 0xFFFFFFFFu;
+                }
+            }
+        }
+        store_tile<B, LPT>(a, t, l, x0, y0);
+    }
+    add_counts(a, lane, changed, mag, bond, fresh);
+}
+
+template <int B, int LPT>
+hipError_t launch_one(const NeSubArgs& a, bool balanced, hipStream_t s)
+{
+    if (balanced) {
+        constexpr int TPW = bal_tiles_per_wave<B, LPT>();
+        static_assert(TPW >= 1, "a sub-lattice must fit the LDS budget");
+        const uint32_t blocks = (a.ntiles + TPW - 1) / TPW;
+        if (a.ntiles == 1)
+            hipLaunchKernelGGL((k_ne_bal<B, LPT, true>), dim3(blocks), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_ne_bal<B, LPT, false>), dim3(blocks), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     constexpr int TPW = tiles_per_wave<B, LPT>();
     static_assert(TPW >= 1, "a sub-lattice must fit the LDS budget");
     const uint32_t blocks = (a.ntiles + TPW - 1) / TPW;
@@ -328,37 +458,37 @@ hipError_t launch_one(const NeSubArgs& a, hipStream_t s)
 }
 
 template <int B>
-hipError_t launch_side(const NeSubArgs& a, int lambda, hipStream_t s)
+hipError_t launch_side(const NeSubArgs& a, int lambda, bool balanced, hipStream_t s)
 {
     switch (lambda) {
-        case 2: return launch_one<B, 1>(a, s);
-        case 4: return launch_one<B, 2>(a, s);
-        case 8: return launch_one<B, 4>(a, s);
-        case 16: return launch_one<B, 8>(a, s);
-        case 32: return launch_one<B, 16>(a, s);
-        case 64: return launch_one<B, 32>(a, s);
-        case 128: return launch_one<B, 64>(a, s);
+        case 2: return launch_one<B, 1>(a, balanced, s);
+        case 4: return launch_one<B, 2>(a, balanced, s);
+        case 8: return launch_one<B, 4>(a, balanced, s);
+        case 16: return launch_one<B, 8>(a, balanced, s);
+        case 32: return launch_one<B, 16>(a, balanced, s);
+        case 64: return launch_one<B, 32>(a, balanced, s);
+        case 128: return launch_one<B, 64>(a, balanced, s);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool ne_sub_supported(uint32_t L, int B, int lambda)
+bool ne_sub_supported(uint32_t L, int B, int lambda, bool balanced)
 {
     if (B != 8 && B != 16 && B != 32 && B != 64) return false;
     if (L % (uint32_t)B != 0) return false;
     if (lambda < 2 || lambda > 128 || (lambda & (lambda - 1)) != 0) return false;
-    return 2 * lambda <= B * B;
+    return (balanced ? 8 : 2) * lambda <= B * B;
 }
 
-hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, hipStream_t s)
+hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, bool balanced, hipStream_t s)
 {
     switch (B) {
-        case 8: return launch_side<8>(a, lambda, s);
-        case 16: return launch_side<16>(a, lambda, s);
-        case 32: return launch_side<32>(a, lambda, s);
-        case 64: return launch_side<64>(a, lambda, s);
+        case 8: return launch_side<8>(a, lambda, balanced, s);
+        case 16: return launch_side<16>(a, lambda, balanced, s);
+        case 32: return launch_side<32>(a, lambda, balanced, s);
+        case 64: return launch_side<64>(a, lambda, balanced, s);
     }
     return hipErrorInvalidValue;
 }

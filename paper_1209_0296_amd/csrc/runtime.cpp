@@ -41,6 +41,16 @@ sl_status hip_fail(hipError_t e, const char* what)
     return fail(SL_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+bool is_sub_lattice(int model) { return model == SL_NE_SUBLATTICE || model == SL_NE_SUBLATTICE_BALANCED; }
+
+// Sweep indices stay below this: the launch index (2 or 4 per sweep) is 32-bit.
+uint64_t sweep_limit(int model)
+{
+    if (model == SL_NE_SUBLATTICE) return 1ull << 31;
+    if (model == SL_NE_SUBLATTICE_BALANCED) return 1ull << 30;
+    return 1ull << 32;
+}
+
 int kind_of(const sl_params* p)
 {
     if (p->model != SL_ISING) return KIND_NE;
@@ -52,7 +62,8 @@ sl_status validate(const sl_params* p)
     if (!p) return fail(SL_E_INVALID, "params is NULL");
     if (p->abi_version != SL_ABI_VERSION)
         return fail(SL_E_INVALID, "abi_version %u != %u", p->abi_version, SL_ABI_VERSION);
-    if (p->model != SL_ISING && p->model != SL_NORTH_EAST && p->model != SL_NE_SUBLATTICE)
+    if (p->model != SL_ISING && p->model != SL_NORTH_EAST && p->model != SL_NE_SUBLATTICE &&
+        p->model != SL_NE_SUBLATTICE_BALANCED)
         return fail(SL_E_INVALID, "unknown model %d", p->model);
     if (p->dim != 2 && p->dim != 3) return fail(SL_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
     if (p->L < 2 || (p->L & 1))
@@ -76,17 +87,20 @@ sl_status validate(const sl_params* p)
         if (p->init == SL_INIT_COLD)
             return fail(SL_E_INVALID, "NE lattices start from Bernoulli(c) or a buffer");
     }
-    if (p->model == SL_NE_SUBLATTICE) {
-        const int B = p->ne_side, lam = p->ne_lambda;
-        if (B < 2 || lam < 1 || p->L % B != 0 || (B * B) % (2 * lam) != 0)
-            return fail(SL_E_INVALID, "sub-lattices need L %% B == 0 and B^2 %% (2 lambda) == 0 "
-                                      "(L %d, B %d, lambda %d)", p->L, B, lam);
-        if (!ne_sub_supported((uint32_t)p->L, B, lam))
+    if (is_sub_lattice(p->model)) {
+        const bool bal = p->model == SL_NE_SUBLATTICE_BALANCED;
+        const int B = p->ne_side, lam = p->ne_lambda, per = bal ? 8 : 2;
+        if (B < 2 || (B & 1) || lam < 1 || p->L % B != 0 || (B * B) % (per * lam) != 0)
+            return fail(SL_E_INVALID, "sub-lattices need an even B with L %% B == 0 and "
+                                      "B^2 %% (%d lambda) == 0 (L %d, B %d, lambda %d)",
+                        per, p->L, B, lam);
+        if (!ne_sub_supported((uint32_t)p->L, B, lam, bal))
             return fail(SL_E_UNSUPPORTED, "the sub-lattice kernels take B in {8,16,32,64} and "
                                           "lambda a power of two in [2,128] (B %d, lambda %d)",
                         B, lam);
-        if (p->t0 >= (1ull << 31))
-            return fail(SL_E_OVERFLOW, "t0 must be < 2^31 (two launch indices per sweep)");
+        if (p->t0 >= sweep_limit(p->model))
+            return fail(SL_E_OVERFLOW, "t0 must be < %llu (launch indices are 32-bit)",
+                        (unsigned long long)sweep_limit(p->model));
     }
     if (p->t0 >= (1ull << 32)) return fail(SL_E_OVERFLOW, "t0 must be < 2^32");
     if (p->record_capacity < 1 || p->record_capacity > (1ull << 32))
@@ -249,7 +263,7 @@ sl_launch auto_launch(const sl_lattice* h)
 
 sl_status check_launch(const sl_lattice* h, sl_launch* l)
 {
-    if (h->params.model == SL_NE_SUBLATTICE) {
+    if (is_sub_lattice(h->params.model)) {
         if (l->mode != SL_MODE_AUTO)
             return fail(SL_E_UNSUPPORTED, "NE sub-lattice lattices have one schedule (SL_MODE_AUTO)");
         return SL_OK;
@@ -304,13 +318,16 @@ sl_status enqueue_observe(sl_lattice* h, uint64_t slot)
 
 // Paper Sec. 3.2, NE algorithm with random sub-lattices: per sweep, launch
 // 2t reads the current copy and writes the other, launch 2t+1 reads that and
-// writes the current copy back.  Both add their accepted counts to the
-// sweep's record slot.  The lattice part of a sweep's record is measured by
+// writes the current copy back (balanced variant: launches 4t .. 4t+3,
+// alternating the copies the same way).  All add their accepted counts to
+// the sweep's record slot.  The lattice part of a sweep's record is measured by
 // the first launch of the next sweep from the state it loads; after the last
 // sweep of the call a separate pass (both colours, no update) measures it.
 sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
 {
     const int B = h->params.ne_side, lam = h->params.ne_lambda;
+    const bool bal = h->params.model == SL_NE_SUBLATTICE_BALANCED;
+    const int per = bal ? 4 : 2;  // launches per sweep
     const uint32_t L = (uint32_t)h->params.L;
     NeSubArgs na{};
     na.L = L;
@@ -330,16 +347,16 @@ sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
         const uint64_t t = h->next_t + i;
         na.acc = slot_ptr(h, h->pending + i);
         hipError_t e = hipSuccess;
-        for (int half = 0; half < 2 && e == hipSuccess; ++half) {
-            uint8_t** from = half == 0 ? cur : oth;
-            uint8_t** to = half == 0 ? oth : cur;
+        for (int k = 0; k < per && e == hipSuccess; ++k) {
+            uint8_t** from = (k & 1) == 0 ? cur : oth;
+            uint8_t** to = (k & 1) == 0 ? oth : cur;
             na.src[0] = from[0];
             na.src[1] = from[1];
             na.dst[0] = to[0];
             na.dst[1] = to[1];
-            na.launch = (uint32_t)(2 * t + (uint64_t)half);
-            na.obs = (half == 0 && i > 0) ? slot_ptr(h, h->pending + i - 1) : nullptr;
-            e = launch_ne_sub(na, B, lam, h->stream);
+            na.launch = (uint32_t)((uint64_t)per * t + (uint64_t)k);
+            na.obs = (k == 0 && i > 0) ? slot_ptr(h, h->pending + i - 1) : nullptr;
+            e = launch_ne_sub(na, B, lam, bal, h->stream);
         }
         sl_status st = SL_OK;
         if (e != hipSuccess) {
@@ -411,7 +428,7 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
     h->cur = 0;
     h->table_n = build_table(params, h->table);
     h->launch = auto_launch(h);
-    if (params->model == SL_NE_SUBLATTICE) h->launch = sl_launch{};
+    if (is_sub_lattice(params->model)) h->launch = sl_launch{};
     h->stage = nullptr;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->stage),
                                  params->record_capacity * sizeof(sl_record), hipHostMallocDefault);
@@ -459,7 +476,7 @@ sl_status sl_set_launch(sl_lattice* h, const sl_launch* launch)
 {
     if (!h || !launch) return fail(SL_E_INVALID, "NULL argument");
     sl_launch l = *launch;
-    if (l.mode == SL_MODE_AUTO && h->params.model != SL_NE_SUBLATTICE) l = auto_launch(h);
+    if (l.mode == SL_MODE_AUTO && !is_sub_lattice(h->params.model)) l = auto_launch(h);
     sl_status st = check_launch(h, &l);
     if (st != SL_OK) return st;
     h->launch = l;
@@ -481,10 +498,10 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
         return fail(SL_E_STATE, "%llu unread records + %llu sweeps exceed record_capacity %llu; "
                                 "call sl_measure first", (unsigned long long)h->pending,
                     (unsigned long long)n, (unsigned long long)h->params.record_capacity);
-    const uint64_t t_end = h->params.model == SL_NE_SUBLATTICE ? (1ull << 31) : (1ull << 32);
+    const uint64_t t_end = sweep_limit(h->params.model);
     if (h->next_t + n > t_end)
         return fail(SL_E_OVERFLOW, "sweep index would reach %llu", (unsigned long long)t_end);
-    if (h->params.model == SL_NE_SUBLATTICE) return sweep_ne_sub(h, n);
+    if (is_sub_lattice(h->params.model)) return sweep_ne_sub(h, n);
     SweepArgs a = args_of(h);
     for (uint64_t i = 0; i < n; ++i) {
         a.t = (uint32_t)(h->next_t + i);

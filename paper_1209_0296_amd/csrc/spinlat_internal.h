@@ -76,7 +76,7 @@ struct NeSubArgs {
     uint8_t* dst[2];            // colour arrays after the launch
     uint32_t L, Lh, tiles_x, ntiles;
     uint32_t key0, key1;        // Philox key = seed
-    uint32_t launch;            // 2 t for the first launch of sweep t, 2 t + 1 for the second
+    uint32_t launch;            // launch index: 2 t, 2 t + 1 (balanced: 4 t .. 4 t + 3)
     uint32_t thr_m1_up;         // NE up-flip threshold minus one (accept iff word <= it)
     uint32_t thr_m1_down;       // NE down-flip threshold minus one
     uint32_t never;             // bit 0: up-flip threshold is 0; bit 1: down-flip threshold is 0
@@ -85,8 +85,11 @@ struct NeSubArgs {
                                 // unflipped of the launch-start lattice
 };
 
-// B in {8, 16, 32, 64}, L % B == 0, lambda a power of two in [2, 128], 2 lambda <= B^2.
-bool ne_sub_supported(uint32_t L, int B, int lambda);
-hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, hipStream_t s);
+// B in {8, 16, 32, 64}, L % B == 0, lambda a power of two in [2, 128],
+// 2 lambda <= B^2 (balanced variant: 8 lambda <= B^2).
+bool ne_sub_supported(uint32_t L, int B, int lambda, bool balanced);
+// balanced: colour 0 then colour 1 per iteration, P/(8 lambda) iterations
+// (four launches per sweep); else q = P/(2 lambda) iterations (two launches)
+hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, bool balanced, hipStream_t s);
 
 }  // namespace spinlat

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspinlat.so")
 
 ABI_VERSION = 2
-ISING, NORTH_EAST, NE_SUBLATTICE = 0, 1, 2
+ISING, NORTH_EAST, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED = 0, 1, 2, 3
 INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
 MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
 MODE_HALF_WINDOW, MODE_FUSED_WINDOW = 4, 5

@@ -50,6 +50,10 @@ def _status(p):
     (dict(model=2, L=64, ne_side=8, ne_lambda=1), 2), (dict(model=2, L=96, ne_side=12, ne_lambda=4), 2),
     (dict(model=2, L=256, ne_side=128, ne_lambda=16), 2), (dict(model=2, ne_lambda=256), 2),
     (dict(model=2, dim=3), 1), (dict(model=2, c=1.0), 1), (dict(model=2, t0=2 ** 31), 6),
+    # its balanced variant
+    (dict(model=3, L=64, ne_side=8, ne_lambda=16), 1), (dict(model=3, L=64, ne_side=8, ne_lambda=3), 1),
+    (dict(model=3, L=96, ne_side=12, ne_lambda=2), 2), (dict(model=3, t0=2 ** 30), 6),
+    (dict(model=3, init=S.INIT_COLD), 1),
 ])
 def test_invalid_parameters_rejected(kw, code):
     st, _ = _status(S.Params(**kw))
@@ -123,6 +127,12 @@ def test_batch_shapes():
 @pytest.mark.parametrize("B,lam", [(8, 2), (8, 32), (16, 8), (32, 16), (32, 128), (64, 16), (64, 128)])
 def test_sub_lattice_shapes_accepted(B, lam):
     assert _status(S.Params(model=S.NE_SUBLATTICE, L=128, ne_side=B, ne_lambda=lam))[0] == 0
+
+
+@pytest.mark.parametrize("B,lam", [(8, 2), (8, 8), (16, 32), (32, 128), (64, 128)])
+def test_balanced_shapes_accepted(B, lam):
+    p = S.Params(model=S.NE_SUBLATTICE_BALANCED, L=128, ne_side=B, ne_lambda=lam)
+    assert _status(p)[0] == 0
 
 
 def test_sub_lattice_jobs_not_batched():

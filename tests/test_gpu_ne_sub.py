@@ -95,3 +95,35 @@ def test_benchmarked_size_matches_oracle():
     o_s, o_r = run_oracle(p, 3)
     np.testing.assert_array_equal(g_r, o_r)
     np.testing.assert_array_equal(g_s, o_s)
+
+
+BAL_CASES = [
+    dict(),                                            # B = 32, lambda = 16: 8 iterations per launch
+    dict(L=128, ne_side=16, ne_lambda=8, c=0.1),
+    dict(L=32, ne_side=32, ne_lambda=16, c=0.42),      # one sub-lattice: periodic wrap inside it
+    dict(L=64, ne_side=8, ne_lambda=8, c=0.5),         # lambda = P/8: one iteration per launch
+    dict(L=64, ne_side=8, ne_lambda=2, c=0.45),
+    dict(L=128, ne_side=64, ne_lambda=128, c=0.3),     # 64 lanes on one sub-lattice
+    dict(L=96, ne_side=32, ne_lambda=4, c=0.7),        # partial workgroup, down-flips thresholded
+    dict(L=256, ne_side=64, ne_lambda=16, c=0.2, seed=2 ** 40 + 9),
+]
+
+
+@pytest.mark.parametrize("kw", BAL_CASES, ids=[str(i) for i in range(len(BAL_CASES))])
+def test_balanced_sweeps_match_oracle(kw):
+    kw = dict(kw)
+    kw["model"] = S.NE_SUBLATTICE_BALANCED
+    p = _p(**kw)
+    g_s, g_r = run_gpu(p, 7, chunks=[3, 4])
+    o_s, o_r = run_oracle(p, 7)
+    np.testing.assert_array_equal(g_r, o_r)
+    np.testing.assert_array_equal(g_s, o_s)
+    assert g_r[1:, 3].sum() > 0
+
+
+def test_balanced_benchmark_size_matches_oracle():
+    p = _p(model=S.NE_SUBLATTICE_BALANCED, L=4096, c=0.1, seed=2027, record_capacity=8)
+    g_s, g_r = run_gpu(p, 2)
+    o_s, o_r = run_oracle(p, 2)
+    np.testing.assert_array_equal(g_r, o_r)
+    np.testing.assert_array_equal(g_s, o_s)

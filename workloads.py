@@ -16,7 +16,7 @@ import numpy as np
 TC_2D = 2.0 / math.log(1.0 + math.sqrt(2.0))  # exact 2D Ising critical temperature
 
 # name -> keyword arguments of Params (model 0 = Ising, 1 = North-East by
-# checkerboard, 2 = North-East by random sub-lattices)
+# checkerboard, 2 = North-East by random sub-lattices, 3 = its balanced variant)
 CONFIGS = {
     # 64x64, cold start, T = 2.269, 1000 sweeps, records every sweep
     "ising2d_L64": dict(model=0, dim=2, L=64, two_s=1, J=1.0, h=0.0, T=2.269, seed=1, init=0,
@@ -36,6 +36,9 @@ CONFIGS = {
     # sub-lattices, lambda = 16 (the paper's best setting, Fig. 5)
     "ne2d_sub_L4096": dict(model=2, dim=2, L=4096, two_s=1, c=0.1, seed=1, init=1, sweeps=100000,
                            ne_side=32, ne_lambda=16),
+    # its balanced variant (colour 0, then colour 1 sites; four launches per sweep)
+    "ne2d_subbal_L4096": dict(model=3, dim=2, L=4096, two_s=1, c=0.1, seed=1, init=1,
+                              sweeps=100000, ne_side=32, ne_lambda=16),
 }
 
 # critical-temperature estimates used only to place temperatures (results do
