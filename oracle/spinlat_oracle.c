@@ -186,6 +186,8 @@ void or_init(const or_params* p, int8_t* s)
     const int L = p->L;
     const int nz = (p->dim == 3) ? L : 1;
     const uint64_t bern_thr = or_threshold_from_prob(p->c);
+    /* every site is independent: rows are shared out among threads */
+#pragma omp parallel for schedule(static) collapse(2)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {

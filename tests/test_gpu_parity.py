@@ -246,6 +246,13 @@ def test_benchmarked_sizes(name, nsweeps):
     _check(sp, nsweeps, launch=AUTO, nthreads=16)
 
 
+def test_out_of_cache_size():
+    """2D L = 32768 (1 GiB per copy, 2 GiB buffer; byte offsets past 2^31): one
+    sweep in the benchmarked schedule, whole lattice and records."""
+    sp = S.Params(L=32768, T=2.269, seed=1, record_capacity=4)
+    _check(sp, 1, launch=AUTO, nthreads=16)
+
+
 @pytest.mark.parametrize("T", [2.0, 2.6])
 def test_ising2d_L8192_other_temperatures(T):
     sp = S.Params(L=8192, T=T, seed=1, record_capacity=8)

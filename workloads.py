@@ -24,6 +24,10 @@ CONFIGS = {
     # 8192x8192, random +-1 start, T in {2.0, 2.269, 2.6}, 10^4 sweeps
     "ising2d_L8192": dict(model=0, dim=2, L=8192, two_s=1, J=1.0, h=0.0, T=2.269, seed=1, init=1,
                           sweeps=10000, temperatures=(2.0, 2.269, 2.6)),
+    # 32768x32768 (1 GiB per lattice copy, beyond the 256 MB last-level cache): the
+    # same sweep measured against HBM itself
+    "ising2d_L32768": dict(model=0, dim=2, L=32768, two_s=1, J=1.0, h=0.0, T=2.269, seed=1, init=1,
+                           sweeps=1000),
     # 256^3 spin-1/2 and spin-1, random start, T = 0.9..1.1 x critical estimate, 5000 sweeps
     "ising3d_L256_s12": dict(model=0, dim=3, L=256, two_s=1, J=1.0, h=0.0, T=4.5115, seed=1,
                              init=1, sweeps=5000),
