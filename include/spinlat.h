@@ -148,7 +148,10 @@ typedef enum sl_mode {
     SL_MODE_FUSED = 3,        /* row-group streaming, both colours in one launch per sweep
                                  with the colour-0 halo rows recomputed (2D only) */
     SL_MODE_HALF_WINDOW = 4,  /* as HALF with 64-lane column windows (any shape) */
-    SL_MODE_FUSED_WINDOW = 5  /* as FUSED with 64-lane column windows and halo lanes */
+    SL_MODE_FUSED_WINDOW = 5, /* as FUSED with 64-lane column windows and halo lanes */
+    SL_MODE_RESIDENT = 6      /* small lattices (both colours <= 48 KiB): one workgroup keeps
+                                 the lattice in LDS and runs up to 4096 whole sweeps per
+                                 launch; the default for lattices of at most 16 KiB */
 } sl_mode;
 
 typedef struct sl_launch {

@@ -165,24 +165,18 @@ __global__ void __launch_bounds__(kBlock) k_fold(unsigned long long* acc, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Direct half-sweep: each thread updates its 4 sites reading the neighbours
-// straight from the other colour array.  With update == 0 it only
-// accumulates the observables of the current state (record r_0).
+// Direct update of one 4-site word gi of colour c: the neighbours are read
+// straight from the other colour array (global memory, or LDS in the resident
+// kernel).  With update == 0 only the observables of the current state are
+// accumulated (record r_0).
 template <int KIND, int DIM>
-__global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
+__device__ __forceinline__ void simple_word(uint8_t* own, const int8_t* oth, const Geom& g, uint32_t c,
+                                            uint64_t gi, uint32_t t, int update, const PhiloxKey& ks,
+                                            const uint64_t* lut, int32_t& q_bond, int32_t& q_mag,
+                                            int32_t& q_acc, int32_t& q_unfl)
 {
-    __shared__ uint64_t lut[kMaxLut];
-    for (int i = threadIdx.x; i < a.lut_n; i += kBlock) lut[i] = a.lut[i];
-    __syncthreads();
-
-    const Geom g = a.g;
-    const uint64_t ngroups = g.nh >> 2;
-    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    int32_t q_bond = 0, q_mag = 0, q_acc = 0, q_unfl = 0;
-    if (gi < ngroups) {
-        const uint32_t c = a.colour;
-        uint8_t* own = a.col[c];
-        const int8_t* oth = reinterpret_cast<const int8_t*>(a.col[c ^ 1u]);
+    {
+        const bool upd = update != 0;
         const uint64_t k0 = gi * 4;
         const uint64_t row = k0 / g.Lh;
         const uint32_t kk0 = (uint32_t)(k0 - row * g.Lh);
@@ -195,14 +189,13 @@ __global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
         const uint64_t r_zp = (uint64_t)wrap_inc(zc, g.L) * g.L + y;
 
         const uint32_t cur = *reinterpret_cast<const uint32_t*>(own + k0);
-        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
         Words4 wa = {{0, 0, 0, 0}}, wb = {{0, 0, 0, 0}};
-        if (a.update) {
+        if (upd) {
             if (KIND == KIND_ISING_ONE) {
-                wa = philox4x32_10((uint32_t)(2 * gi), c, a.t, 0u, ks);
-                wb = philox4x32_10((uint32_t)(2 * gi + 1), c, a.t, 0u, ks);
+                wa = philox4x32_10((uint32_t)(2 * gi), c, t, 0u, ks);
+                wb = philox4x32_10((uint32_t)(2 * gi + 1), c, t, 0u, ks);
             } else {
-                wa = philox4x32_10((uint32_t)gi, c, a.t, 0u, ks);
+                wa = philox4x32_10((uint32_t)gi, c, t, 0u, ks);
             }
         }
         constexpr int z = 2 * DIM;
@@ -216,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
             if (KIND == KIND_NE) {
                 const int north = oth[r_ym * g.Lh + kk];
                 const int east = oth[row * g.Lh + (p ? kside : kk)];
-                nv = a.update ? move_ne(sv, north, east, wa.w[b], lut[0], lut[1]) : sv;
+                nv = upd ? move_ne(sv, north, east, wa.w[b], lut[0], lut[1]) : sv;
                 q_mag += nv & 1;
                 q_unfl += (nv & 2) ? 0 : 1;
                 if (c == 1) {
@@ -228,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
                 int nsum = oth[row * g.Lh + kk] + oth[row * g.Lh + kside] + oth[r_ym * g.Lh + kk] +
                            oth[r_yp * g.Lh + kk];
                 if (DIM == 3) nsum += oth[r_zm * g.Lh + kk] + oth[r_zp * g.Lh + kk];
-                if (!a.update) {
+                if (!upd) {
                     nv = sv;
                 } else if (KIND == KIND_ISING_HALF) {
                     nv = move_ising_half(sv, nsum, wa.w[b], lut, z);
@@ -242,9 +235,67 @@ __global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
             q_acc += (nv != sv) ? 1 : 0;
             out |= (uint32_t)(uint8_t)(int8_t)nv << (8 * b);
         }
-        if (a.update) *reinterpret_cast<uint32_t*>(own + k0) = out;
+        if (upd) *reinterpret_cast<uint32_t*>(own + k0) = out;
+    }
+}
+
+// Direct half-sweep: one thread per 4-site word of colour a.colour.
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
+{
+    __shared__ uint64_t lut[kMaxLut];
+    for (int i = threadIdx.x; i < a.lut_n; i += kBlock) lut[i] = a.lut[i];
+    __syncthreads();
+
+    const uint64_t ngroups = a.g.nh >> 2;
+    const uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t q_bond = 0, q_mag = 0, q_acc = 0, q_unfl = 0;
+    if (gi < ngroups) {
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        simple_word<KIND, DIM>(a.col[a.colour], reinterpret_cast<const int8_t*>(a.col[a.colour ^ 1u]),
+                               a.g, a.colour, gi, a.t, a.update, ks, lut, q_bond, q_mag, q_acc,
+                               q_unfl);
     }
     block_accumulate(q_bond, q_mag, q_acc, q_unfl, a.acc);
+}
+
+// Small lattices: one workgroup holds both colour arrays in LDS and runs
+// `nsweeps` whole sweeps in one launch (colour 0, barrier, colour 1, barrier,
+// record), so the sweep costs no launch.  Record s goes to acc + s slots; the
+// sweep index of sweep s is a.t + s.  The lattice is written back at the end.
+constexpr int kResidentBlock = 512;
+
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(kResidentBlock) k_resident(SweepArgs a, uint32_t nsweeps)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    __shared__ uint64_t lut[kMaxLut];
+    const uint64_t nh = a.g.nh;
+    const uint32_t nwords = (uint32_t)(nh >> 2);
+    for (uint32_t i = threadIdx.x; i < nwords; i += kResidentBlock) {
+        reinterpret_cast<uint32_t*>(sm)[i] = reinterpret_cast<const uint32_t*>(a.col[0])[i];
+        reinterpret_cast<uint32_t*>(sm + nh)[i] = reinterpret_cast<const uint32_t*>(a.col[1])[i];
+    }
+    for (int i = threadIdx.x; i < a.lut_n; i += kResidentBlock) lut[i] = a.lut[i];
+    __syncthreads();
+    const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+    for (uint32_t s = 0; s < nsweeps; ++s) {
+        int32_t q_bond = 0, q_mag = 0, q_acc = 0, q_unfl = 0;
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            uint8_t* own = sm + c * nh;
+            const int8_t* oth = reinterpret_cast<const int8_t*>(sm + (c ^ 1u) * nh);
+            for (uint32_t gi = threadIdx.x; gi < nwords; gi += kResidentBlock)
+                simple_word<KIND, DIM>(own, oth, a.g, c, gi, a.t + s, 1, ks, lut, q_bond, q_mag, q_acc,
+                                       q_unfl);
+            __syncthreads();
+        }
+        block_accumulate(q_bond, q_mag, q_acc, q_unfl, a.acc + (uint64_t)s * kSlotWords);
+    }
+    for (uint32_t i = threadIdx.x; i < nwords; i += kResidentBlock) {
+        reinterpret_cast<uint32_t*>(a.col[0])[i] = reinterpret_cast<const uint32_t*>(sm)[i];
+        reinterpret_cast<uint32_t*>(a.col[1])[i] = reinterpret_cast<const uint32_t*>(sm + nh)[i];
+    }
 }
 
 inline unsigned blocks_for(uint64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -298,6 +349,29 @@ hipError_t launch_overlap(const SweepArgs& a, const int8_t* ref, int ne, unsigne
 {
     hipLaunchKernelGGL(k_overlap, dim3(blocks_for(2 * (a.g.nh >> 2))), dim3(kBlock), 0, s, a, ref,
                        ne, out);
+    return hipGetLastError();
+}
+
+bool resident_supported(const Geom& g) { return 2 * g.nh <= (uint64_t)kResidentLds; }
+
+hipError_t launch_resident(const SweepArgs& a, int kind, uint32_t nsweeps, hipStream_t s)
+{
+    const size_t lds = (size_t)(2 * a.g.nh);
+    if (lds > (size_t)kResidentLds) return hipErrorInvalidValue;
+    const dim3 grid(1), block(kResidentBlock);
+    if (kind == KIND_NE) {
+        hipLaunchKernelGGL((k_resident<KIND_NE, 2>), grid, block, lds, s, a, nsweeps);
+    } else if (a.g.dim == 2) {
+        if (kind == KIND_ISING_HALF)
+            hipLaunchKernelGGL((k_resident<KIND_ISING_HALF, 2>), grid, block, lds, s, a, nsweeps);
+        else
+            hipLaunchKernelGGL((k_resident<KIND_ISING_ONE, 2>), grid, block, lds, s, a, nsweeps);
+    } else {
+        if (kind == KIND_ISING_HALF)
+            hipLaunchKernelGGL((k_resident<KIND_ISING_HALF, 3>), grid, block, lds, s, a, nsweeps);
+        else
+            hipLaunchKernelGGL((k_resident<KIND_ISING_ONE, 3>), grid, block, lds, s, a, nsweeps);
+    }
     return hipGetLastError();
 }
 

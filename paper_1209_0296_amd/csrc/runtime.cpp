@@ -8,6 +8,7 @@
 // drain the per-sweep record ring.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -224,17 +225,39 @@ bool lut32_ok(const sl_lattice* h)
     return true;
 }
 
-// Default schedule for a shape: 2D lattices take one fused launch per sweep,
-// 3D lattices two in-place half-sweeps (a fused 3D sweep would recompute a
-// halo in two directions).  Strip height H and words per lane D are the
-// fastest measured on MI355X for 2D L = 8192 (spin-1/2: H 8, D 4), NE
-// L = 4096 (H 4, D 2) and 3D L = 256 (H 4, D 4); other widths are tried in
-// order when D does not divide the row, and shapes the whole-row kernels
-// cannot take fall back to the window kernels.
+// Default schedule for a shape, from timings on MI355X: lattices of at most
+// 16 KiB run resident in LDS; up to 2^18 sites (2D) or 2^20 sites (3D) the
+// direct kernel; beyond that
+// 2D lattices take one fused launch per sweep and 3D lattices two in-place
+// half-sweeps (a fused 3D sweep would recompute a halo in two directions).
+// Strip height H and words per lane D: 2D spin-1/2 H 8 with D 4 from
+// L = 8192 (D 2 below, e.g. 13 us against 18 us per sweep at L = 2048), NE
+// H 4 D 2, 3D H 4 D 4; other widths are tried in order when D does not divide
+// the row, and shapes the whole-row kernels cannot take fall back to the
+// window kernels.
+// Lattices up to this many bytes (both colours) run in the resident mode by
+// default; kResidentChunk sweeps at most per launch.
+constexpr uint64_t kResidentAuto = 16 * 1024;
+constexpr uint64_t kSimpleAuto2 = 1u << 18;  // sites (2D L <= 512)
+constexpr uint64_t kSimpleAuto3 = 1u << 20;  // sites (3D L <= 101)
+constexpr uint64_t kResidentChunk = 4096;
+
 sl_launch auto_launch(const sl_lattice* h)
 {
     const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
                     0u, h->lay.nh};
+    if (2 * h->lay.nh <= kResidentAuto) {  // launch-bound sizes: all sweeps in one launch
+        sl_launch r{};
+        r.mode = SL_MODE_RESIDENT;
+        return r;
+    }
+    // latency-bound sizes: the direct kernel's short launches beat the strip walk
+    // of the row kernels (measured: 2D up to 512^2, 3D up to 96^3)
+    if (h->lay.nsites <= (h->params.dim == 2 ? kSimpleAuto2 : kSimpleAuto3)) {
+        sl_launch r{};
+        r.mode = SL_MODE_SIMPLE;
+        return r;
+    }
     const bool fused = h->params.dim == 2;
     int H = 8, Ds[3] = {4, 2, 1};
     if (h->params.dim == 3) {
@@ -243,7 +266,7 @@ sl_launch auto_launch(const sl_lattice* h)
         H = 4;
         Ds[0] = 2;
         Ds[1] = 4;
-    } else if (h->kind == KIND_ISING_ONE) {
+    } else if (h->kind == KIND_ISING_ONE || h->params.L < 8192) {
         Ds[0] = 2;
         Ds[1] = 4;
     }
@@ -272,6 +295,12 @@ sl_status check_launch(const sl_lattice* h, sl_launch* l)
                     0u, h->lay.nh};
     switch (l->mode) {
         case SL_MODE_SIMPLE:
+            return SL_OK;
+        case SL_MODE_RESIDENT:
+            if (!resident_supported(g) || l->tile_rows != 0 || l->tile_words != 0)
+                return fail(SL_E_UNSUPPORTED, "the resident mode holds at most %d bytes of lattice "
+                            "(this one has %llu) and takes no tile sizes", kResidentLds,
+                            (unsigned long long)(2 * h->lay.nh));
             return SL_OK;
         case SL_MODE_HALF:
         case SL_MODE_FUSED: {
@@ -503,6 +532,23 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
         return fail(SL_E_OVERFLOW, "sweep index would reach %llu", (unsigned long long)t_end);
     if (is_sub_lattice(h->params.model)) return sweep_ne_sub(h, n);
     SweepArgs a = args_of(h);
+    if (h->launch.mode == SL_MODE_RESIDENT) {
+        for (uint64_t i = 0; i < n;) {
+            const uint32_t k = (uint32_t)std::min<uint64_t>(n - i, kResidentChunk);
+            a.t = (uint32_t)(h->next_t + i);
+            a.acc = slot_ptr(h, h->pending + i);
+            hipError_t e = launch_resident(a, h->kind, k, h->stream);
+            if (e != hipSuccess) {
+                h->next_t += i;
+                h->pending += i;
+                return hip_fail(e, "resident sweep launch");
+            }
+            i += k;
+        }
+        h->next_t += n;
+        h->pending += n;
+        return SL_OK;
+    }
     for (uint64_t i = 0; i < n; ++i) {
         a.t = (uint32_t)(h->next_t + i);
         a.acc = slot_ptr(h, h->pending + i);

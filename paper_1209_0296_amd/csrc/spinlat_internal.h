@@ -48,6 +48,11 @@ hipError_t launch_init(const SweepArgs& a, int kind, int init_mode, uint32_t ber
 hipError_t launch_from_natural(const SweepArgs& a, const int8_t* nat, hipStream_t s);
 hipError_t launch_to_natural(const SweepArgs& a, int8_t* nat, hipStream_t s);
 hipError_t launch_clear_flags(const SweepArgs& a, hipStream_t s);
+// Small lattices: both colour arrays in the LDS of one workgroup, nsweeps
+// sweeps per launch, record s into a.acc + s slots, sweep index a.t + s.
+constexpr int kResidentLds = 48 * 1024;  // bytes of lattice one workgroup holds
+bool resident_supported(const Geom& g);
+hipError_t launch_resident(const SweepArgs& a, int kind, uint32_t nsweeps, hipStream_t s);
 // out (one int64, zeroed by the caller) += sum_i v_i v_i^ref; ne: v = 2n - 1
 hipError_t launch_overlap(const SweepArgs& a, const int8_t* ref, int ne, unsigned long long* out,
                           hipStream_t s);

@@ -16,6 +16,7 @@ FUSED = (S.MODE_FUSED, 0, 0)
 HALF_W = (S.MODE_HALF_WINDOW, 0, 0)
 FUSED_W = (S.MODE_FUSED_WINDOW, 0, 0)
 AUTO = (S.MODE_AUTO, 0, 0)
+RESIDENT = (S.MODE_RESIDENT, 0, 0)
 # whole-row kernels: (mode, rows per strip, words per lane)
 ROW = [(m, H, D) for m in (S.MODE_HALF, S.MODE_FUSED) for H, D in ((3, 1), (8, 2), (5, 4))]
 
@@ -35,7 +36,7 @@ def _check(sp, nsweeps, launch=None, chunks=None, nthreads=0):
     np.testing.assert_array_equal(g_s, o_s)
 
 
-@pytest.mark.parametrize("launch", [SIMPLE, HALF, FUSED, HALF_W, FUSED_W, AUTO])
+@pytest.mark.parametrize("launch", [SIMPLE, HALF, FUSED, HALF_W, FUSED_W, RESIDENT, AUTO])
 def test_ising2d_L64_cold_1000_sweeps(launch):
     """64x64, J=1, T=2.269, cold start, seed 1, 1000 sweeps, every record."""
     sp = S.Params(L=64, T=2.269, init=S.INIT_COLD, seed=1, record_capacity=1001)
@@ -52,7 +53,7 @@ SHAPES_2D = [8, 16, 40, 64, 72, 136, 512, 1024, 1040, 2048]
 
 @pytest.mark.parametrize("L", SHAPES_2D)
 @pytest.mark.parametrize("two_s", [1, 2])
-@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, FUSED_W, AUTO] + ROW)
+@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, FUSED_W, RESIDENT, AUTO] + ROW)
 def test_ising2d_shapes(L, two_s, launch):
     n = 12 if L >= 512 else 25
     sp = S.Params(L=L, two_s=two_s, T=2.0 if two_s == 1 else 1.5, seed=7 + L, record_capacity=64)
@@ -70,7 +71,7 @@ def test_strip_heights(rows, mode):
 
 @pytest.mark.parametrize("L", [8, 16, 24, 40, 64, 128])
 @pytest.mark.parametrize("two_s", [1, 2])
-@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, (S.MODE_HALF_WINDOW, 5, 0), AUTO,
+@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, (S.MODE_HALF_WINDOW, 5, 0), AUTO, RESIDENT,
                                     (S.MODE_HALF, 3, 1), (S.MODE_HALF, 8, 2), (S.MODE_HALF, 4, 4)])
 def test_ising3d_shapes(L, two_s, launch):
     sp = S.Params(dim=3, L=L, two_s=two_s, T=4.5 if two_s == 1 else 3.2, seed=3 + L,
@@ -80,10 +81,37 @@ def test_ising3d_shapes(L, two_s, launch):
 
 @pytest.mark.parametrize("L", [8, 32, 72, 1040, 2048])
 @pytest.mark.parametrize("c", [0.05, 0.2, 0.6])
-@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, FUSED_W, AUTO] + ROW)
+@pytest.mark.parametrize("launch", [SIMPLE, HALF_W, FUSED_W, RESIDENT, AUTO] + ROW)
 def test_ne_shapes(L, c, launch):
     sp = S.Params(model=S.NORTH_EAST, L=L, c=c, seed=11, record_capacity=64)
     _check(sp, 12 if L > 512 else 30, launch=launch)
+
+
+def test_resident_chunks_and_mixed_modes():
+    """More sweeps than one resident launch runs (4096), then a switch to the
+    fused mode and back, on an 8x8 and a 48x48 lattice."""
+    sp = S.Params(L=8, T=2.269, seed=21, record_capacity=5001)
+    _check(sp, 5000, launch=RESIDENT)
+    sp = S.Params(L=48, two_s=2, T=1.7, seed=22, record_capacity=64)
+    o_s, o_r = run_oracle(sp, 30)
+    import paper_1209_0296_amd as P
+
+    lat = P.Lattice(sp)
+    recs = [P.records_to_array(lat.measure())]
+    for mode, n in ((RESIDENT, 7), (FUSED, 5), (RESIDENT, 18)):
+        lat.set_launch(*mode)
+        lat.sweep(n)
+        recs.append(P.records_to_array(lat.measure()))
+    np.testing.assert_array_equal(np.vstack(recs), o_r)
+    np.testing.assert_array_equal(lat.spins(), o_s)
+    lat.close()
+
+
+def test_resident_refuses_large_lattices():
+    lat = S.Lattice(S.Params(L=256, seed=1))
+    with pytest.raises(S.SpinlatError):
+        lat.set_launch(*RESIDENT)
+    lat.close()
 
 
 def test_zero_threshold_tables_use_window_kernels():
