@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the 2D L=32768, 3D L=256 and NE L=4096 lines")
+                    help="skip the 2D L=64 and L=32768, 3D L=256 and NE L=4096 lines")
     ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--served-jobs", type=int, default=4096,
                     help="jobs in the served Poisson stream (0: skip serving)")
@@ -214,8 +214,8 @@ def main():
           f"{main_res['ms_per_step']:.4f} ms/sweep", file=sys.stderr, flush=True)
     secondary = []
     if not args.no_secondary:
-        for key in ("ising2d_L32768", "ising3d_L256_s12", "ising3d_L256_s1", "ne2d_L4096",
-                    "ne2d_sub_L4096", "ne2d_subbal_L4096"):
+        for key in ("ising2d_L64", "ising2d_L32768", "ising3d_L256_s12", "ising3d_L256_s1",
+                    "ne2d_L4096", "ne2d_sub_L4096", "ne2d_subbal_L4096"):
             r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)
