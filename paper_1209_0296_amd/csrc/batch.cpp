@@ -374,17 +374,12 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     }
     if (n_eff == 0) return SL_OK;
 
-    // work lists grouped by class (kind, dim, words per lane)
-    struct Cls {
-        int kind, dim, D;
-        uint32_t begin, count;
-    };
-    std::vector<Cls> classes;
+    // the work list grouped by kernel variant (kind, dim, words per lane), so
+    // neighbouring workgroups of the one launch run the same code
     uint64_t nwg = 0;
     for (int kind : {KIND_ISING_HALF, KIND_ISING_ONE, KIND_NE})
         for (int dim : {2, 3})
             for (int D : {4, 2, 1, 0}) {
-                Cls c{kind, dim, D, (uint32_t)nwg, 0};
                 for (uint32_t j = 0; j < top; ++j) {
                     const JobHost& J = b->jobs[j];
                     if (!J.used || !budget[j] || J.kind != kind || J.params.dim != dim || J.geom.D != D)
@@ -396,9 +391,7 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
                                     (unsigned long long)max_wg(&b->cfg));
                     for (uint32_t w = 0; w < k; ++w) b->h_wgs[nwg + w] = BatchWG{j, w * per};
                     nwg += k;
-                    c.count += k;
                 }
-                if (c.count) classes.push_back(c);
             }
     for (uint32_t j = 0; j < top; ++j) {
         uint32_t* d = b->h_dyn + kDynWords * j;
@@ -421,7 +414,6 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
         for (uint32_t colour = 0; colour < 2 && e == hipSuccess; ++colour)
             e = launch_batch_all(d_jobs(b), d_dyn(b), d_wgs(b), (uint32_t)nwg, colour, (uint32_t)s,
                                  b->stream);
-    (void)classes;
     if (e != hipSuccess) return hip_fail(e, "batch sweep");
     for (uint32_t j = 0; j < top; ++j) {
         JobHost& J = b->jobs[j];
