@@ -231,8 +231,9 @@ bool lut32_ok(const sl_lattice* h)
 // 2D lattices take one fused launch per sweep and 3D lattices two in-place
 // half-sweeps (a fused 3D sweep would recompute a halo in two directions).
 // Strip height H and words per lane D: 2D spin-1/2 H 8 with D 4 from
-// L = 8192 (D 2 below, e.g. 13 us against 18 us per sweep at L = 2048), NE
-// H 4 D 2, 3D H 4 D 4; other widths are tried in order when D does not divide
+// L = 8192 (D 2 below, e.g. 13 us against 18 us per sweep at L = 2048) and
+// H 16 from L = 16384 (625 us against 686 us at L = 32768), NE H 4 D 2,
+// 3D H 4 D 4; other widths are tried in order when D does not divide
 // the row, and shapes the whole-row kernels cannot take fall back to the
 // window kernels.
 // Lattices up to this many bytes (both colours) run in the resident mode by
@@ -269,6 +270,8 @@ sl_launch auto_launch(const sl_lattice* h)
     } else if (h->kind == KIND_ISING_ONE || h->params.L < 8192) {
         Ds[0] = 2;
         Ds[1] = 4;
+    } else if (h->params.L >= 16384) {
+        H = 16;  // fewer recomputed halo rows; enough strips to fill the chip
     }
     sl_launch l{};
     for (int D : Ds)
