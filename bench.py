@@ -109,8 +109,9 @@ def time_workload(S, torch, name, cfg, steps, warmup, T=None):
     }
 
 
-def cpu_baseline(cfg, sweeps, threads):
-    """The oracle as it is, on the host cores, on `sweeps` sweeps of the same lattice."""
+def cpu_baseline(cfg, sweeps, threads, single_sweeps=2):
+    """The oracle as it is, on the host cores, on `sweeps` sweeps of the same
+    lattice; and on one thread over `single_sweeps` sweeps."""
     import oracle as O
 
     p = O.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
@@ -120,9 +121,16 @@ def cpu_baseline(cfg, sweeps, threads):
     t0 = time.perf_counter()
     O.run(p, s, 0, sweeps, records=True, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": p.nsites * sweeps / dt, "unit": "flip attempts/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{sweeps} sweeps of 2D L={cfg['L']} (records every sweep), {dt:.1f} s"}
+    out = {"value": p.nsites * sweeps / dt, "unit": "flip attempts/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{sweeps} sweeps of 2D L={cfg['L']} (records every sweep), {dt:.1f} s"}
+    if single_sweeps:
+        t0 = time.perf_counter()
+        O.run(p, s, sweeps, single_sweeps, records=True, nthreads=1)
+        d1 = time.perf_counter() - t0
+        out["single_thread_value"] = p.nsites * single_sweeps / d1
+        out["single_thread_sample"] = f"{single_sweeps} further sweeps on 1 thread, {d1:.1f} s"
+    return out
 
 
 def served(args):

@@ -107,8 +107,17 @@ def test_resident_chunks_and_mixed_modes():
     lat.close()
 
 
-def test_resident_refuses_large_lattices():
-    lat = S.Lattice(S.Params(L=256, seed=1))
+@pytest.mark.parametrize("kw", [dict(L=216, T=2.3), dict(dim=3, L=36, two_s=2, T=3.0),
+                                dict(model=S.NORTH_EAST, L=216, c=0.35)])
+def test_resident_largest_lattices(kw):
+    """Lattices of 46656 sites (2D L = 216, 3D L = 36), the largest under the 48 KiB limit."""
+    sp = S.Params(seed=31, record_capacity=32, **kw)
+    _check(sp, 20, launch=RESIDENT)
+
+
+@pytest.mark.parametrize("kw", [dict(L=224), dict(L=256), dict(dim=3, L=40)])
+def test_resident_refuses_large_lattices(kw):
+    lat = S.Lattice(S.Params(seed=1, **kw))
     with pytest.raises(S.SpinlatError):
         lat.set_launch(*RESIDENT)
     lat.close()
