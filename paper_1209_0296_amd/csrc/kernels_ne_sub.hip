@@ -40,6 +40,10 @@
 // from -- the state after the previous sweep -- from the sub-lattices it has
 // just loaded (bonds to the north and east neighbours, which tile the lattice's
 // bonds exactly once), so no separate pass reads the lattice for that record.
+//
+// The balanced variant (k_ne_bal, end of Sec. 3.2) shares the loads, stores and
+// records; its iterations alternate the two colours of the sub-lattice and
+// four launches make a sweep (see the comment above the kernel).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

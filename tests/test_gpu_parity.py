@@ -294,3 +294,21 @@ def test_out_of_cache_size():
 def test_ising2d_L8192_other_temperatures(T):
     sp = S.Params(L=8192, T=T, seed=1, record_capacity=8)
     _check(sp, 2, launch=AUTO, nthreads=16)
+
+
+def test_zero_sweeps_and_single_record_ring():
+    """sweep(0) is a no-op; a ring of one record holds r_0 only, so a sweep
+    fails until it is drained, then each sweep fits exactly."""
+    sp = S.Params(L=64, T=2.0, seed=8, record_capacity=1)
+    o_s, o_r = run_oracle(sp, 3)
+    lat = S.Lattice(sp)
+    lat.sweep(0)
+    with pytest.raises(S.SpinlatError):
+        lat.sweep(1)
+    recs = [S.records_to_array(lat.measure())]
+    for _ in range(3):
+        lat.sweep(1)
+        recs.append(S.records_to_array(lat.measure()))
+    np.testing.assert_array_equal(np.vstack(recs), o_r)
+    np.testing.assert_array_equal(lat.spins(), o_s)
+    lat.close()
