@@ -136,8 +136,8 @@ __global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict_
         for (int s = 0; s < kSub; ++s)
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                sum[q] += (int64_t)slot[s * kQ + q];
-                slot[s * kQ + q] = 0ull;
+                sum[q] += (int64_t)slot[s * kSubStride + q];
+                slot[s * kSubStride + q] = 0ull;
             }
         int64_t* o = out + (f.out_off + i) * kRecordWords;
         o[0] = (int64_t)(f.first_t + i);

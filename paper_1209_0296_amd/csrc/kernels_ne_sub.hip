@@ -252,7 +252,7 @@ __device__ __forceinline__ void add_counts(const NeSubArgs& a, uint32_t lane, in
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) changed += __shfl_xor(changed, off, 64);
     if (lane == 0 && changed != 0)
-        atomicAdd(&a.acc[(blockIdx.x % kSub) * kQ + 2], (unsigned long long)changed);
+        atomicAdd(&a.acc[(blockIdx.x % kSub) * kSubStride + 2], (unsigned long long)changed);
     if (a.obs) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -260,7 +260,7 @@ __device__ __forceinline__ void add_counts(const NeSubArgs& a, uint32_t lane, in
             bond += __shfl_xor(bond, off, 64);
             fresh += __shfl_xor(fresh, off, 64);
         }
-        unsigned long long* o = a.obs + (blockIdx.x % kSub) * kQ;
+        unsigned long long* o = a.obs + (blockIdx.x % kSub) * kSubStride;
         if (lane == 0 && bond != 0) atomicAdd(&o[0], (unsigned long long)bond);
         if (lane == 1 && mag != 0) atomicAdd(&o[1], (unsigned long long)mag);
         if (lane == 2 && fresh != 0) atomicAdd(&o[3], (unsigned long long)fresh);

@@ -153,8 +153,8 @@ __global__ void __launch_bounds__(kBlock) k_fold(unsigned long long* acc, int64_
     for (int s = 0; s < kSub; ++s)
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            sum[q] += (int64_t)slot[s * kQ + q];
-            slot[s * kQ + q] = 0ull;
+            sum[q] += (int64_t)slot[s * kSubStride + q];
+            slot[s * kSubStride + q] = 0ull;
         }
     int64_t* o = out + i * kRecordWords;
     o[0] = (int64_t)(t_first + i);

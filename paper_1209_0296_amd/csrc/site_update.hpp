@@ -78,7 +78,7 @@ __device__ __forceinline__ void block_accumulate(int32_t v0, int32_t v1, int32_t
         int64_t sum = 0;
         for (int w = 0; w < nw; ++w) sum += part[w][threadIdx.x];
         if (sum != 0)
-            atomicAdd(&acc[(blockIdx.x % kSub) * kQ + threadIdx.x], (unsigned long long)sum);
+            atomicAdd(&acc[(blockIdx.x % kSub) * kSubStride + threadIdx.x], (unsigned long long)sum);
     }
 }
 
