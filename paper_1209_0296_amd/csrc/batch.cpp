@@ -1,7 +1,7 @@
 // batch.cpp -- host side of the batch ABI (include/spinlat.h, "Batches").
 //
 // The caller's arena holds, in order: the device job table, the per-job
-// counters {t, record slot, sweeps left}, the work list of the batched
+// counters {t, record slot, sweeps in this call}, the work list of the batched
 // kernels, a fold buffer for record readback, and a heap from which each
 // job's lattice (two colour arrays) and record ring are carved first-fit.
 // Admission by footprint is the heap allocation succeeding.

@@ -1,5 +1,6 @@
-// kernels_simple.hip -- initial state, layout conversion, record folding and
-// the direct (no LDS) half-sweep kernel for gfx950.
+// kernels_simple.hip -- initial state, layout conversion, record folding, the
+// overlap reduction, the direct (no LDS) half-sweep kernel and the resident
+// kernel that runs many sweeps of a small lattice held in LDS, for gfx950.
 //
 // Layout: two colour arrays of L^dim/2 int8 sites (see spinlat_internal.h).
 // One thread owns one 4-byte word = 4 consecutive same-colour sites of one row

@@ -4,8 +4,10 @@
 // build the Metropolis threshold table in double precision (paper Sec. 3.1:
 // P_acc = min[1, exp(-dE/T)]; Sec. 3.2 for the NE model), enqueue the
 // kernels on the caller's stream (one sweep = colour 0 then colour 1, Alg. I
-// steps 5-7; a kernel boundary is the global barrier between the colours) and
-// drain the per-sweep record ring.
+// steps 5-7; a kernel boundary, or a workgroup barrier in the resident mode,
+// separates the colours; the NE sub-lattice algorithms of Sec. 3.2 take two or
+// four launches per sweep), drain the per-sweep record ring, and evaluate the
+// observables of records and lattices.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
