@@ -227,22 +227,23 @@ bool lut32_ok(const sl_lattice* h)
     return true;
 }
 
-// Default schedule for a shape, from timings on MI355X: lattices of at most
-// 16 KiB run resident in LDS; up to 2^18 sites (2D) or 2^20 sites (3D) the
-// direct kernel; beyond that
-// 2D lattices take one fused launch per sweep and 3D lattices two in-place
-// half-sweeps (a fused 3D sweep would recompute a halo in two directions).
-// Strip height H and words per lane D: 2D spin-1/2 H 8 with D 4 from
-// L = 8192 (D 2 below, e.g. 13 us against 18 us per sweep at L = 2048) and
-// H 16 from L = 16384 (625 us against 686 us at L = 32768), NE H 4 D 2,
-// 3D H 4 D 4; other widths are tried in order when D does not divide
-// the row, and shapes the whole-row kernels cannot take fall back to the
-// window kernels.
-// Lattices up to this many bytes (both colours) run in the resident mode by
-// default; kResidentChunk sweeps at most per launch.
+// Default schedule for a shape, from the schedule autotuner's timings on
+// MI355X (us per sweep):
+//   - lattices of at most 16 KiB run resident in LDS (2D L = 64: 2.4);
+//   - 2D up to L = 2048: fused with 2-row strips, 1 word per lane up to
+//     L = 512, else 2 (L = 256: 5.8; 1024: 6.2; 2048: 8.1; the direct kernel
+//     takes 8.5 at these sizes);
+//   - 2D L = 4096: fused, 4-row strips (spin-1/2 16.4 with D 4; spin-1 and NE
+//     D 2); from L = 8192 spin-1/2 takes 8-row strips with D 4 (42.9 at 8192)
+//     and 16-row strips from L = 16384 (625 at 32768); NE keeps H 4 D 2;
+//   - 3D up to L = 160: half-sweeps with 2-row strips, 1 word per lane (L = 128:
+//     10.3 against 14.1 with 4-row strips and D 4); larger: 4-row strips, D 4
+//     (L = 256: 19.3).
+// A fused 3D sweep would recompute a halo in two directions, so 3D uses
+// half-sweeps.  Other widths are tried in order when D does not divide the
+// row, and shapes the whole-row kernels cannot take fall back to the window
+// kernels.
 constexpr uint64_t kResidentAuto = 16 * 1024;
-constexpr uint64_t kSimpleAuto2 = 1u << 18;  // sites (2D L <= 512)
-constexpr uint64_t kSimpleAuto3 = 1u << 20;  // sites (3D L <= 101)
 constexpr uint64_t kResidentChunk = 4096;
 
 sl_launch auto_launch(const sl_lattice* h)
@@ -254,26 +255,28 @@ sl_launch auto_launch(const sl_lattice* h)
         r.mode = SL_MODE_RESIDENT;
         return r;
     }
-    // latency-bound sizes: the direct kernel's short launches beat the strip walk
-    // of the row kernels (measured: 2D up to 512^2, 3D up to 96^3)
-    if (h->lay.nsites <= (h->params.dim == 2 ? kSimpleAuto2 : kSimpleAuto3)) {
-        sl_launch r{};
-        r.mode = SL_MODE_SIMPLE;
-        return r;
-    }
+    const int L = h->params.L;
     const bool fused = h->params.dim == 2;
-    int H = 8, Ds[3] = {4, 2, 1};
+    const bool half_spin = h->kind == KIND_ISING_HALF;
+    int H = 4, Ds[3] = {4, 2, 1};
     if (h->params.dim == 3) {
-        H = 4;
-    } else if (h->kind == KIND_NE) {
-        H = 4;
-        Ds[0] = 2;
-        Ds[1] = 4;
-    } else if (h->kind == KIND_ISING_ONE || h->params.L < 8192) {
-        Ds[0] = 2;
-        Ds[1] = 4;
-    } else if (h->params.L >= 16384) {
-        H = 16;  // fewer recomputed halo rows; enough strips to fill the chip
+        if (L <= 160) {
+            H = 2;
+            Ds[0] = 1, Ds[1] = 2, Ds[2] = 4;
+        }
+    } else if (L <= 512) {
+        H = 2;
+        Ds[0] = 1, Ds[1] = 2, Ds[2] = 4;
+    } else if (L <= 2048) {
+        H = 2;
+        Ds[0] = 2, Ds[1] = 1, Ds[2] = 4;
+    } else if (!half_spin) {
+        H = (h->kind == KIND_NE || L < 8192) ? 4 : 8;
+        Ds[0] = 2, Ds[1] = 4, Ds[2] = 1;
+    } else if (L >= 16384) {
+        H = 16;
+    } else if (L >= 8192) {
+        H = 8;
     }
     sl_launch l{};
     for (int D : Ds)
