@@ -31,6 +31,7 @@ ISING = 0
 NORTH_EAST = 1
 NE_TILES = 2  # North-East model, the paper's random sub-lattice algorithm
 NE_BALANCED = 3  # its balanced variant (red, then white sites; four launches per sweep)
+NE_COUPLED = 4  # NE constraint on the Ising energy with J, h, T (checkerboard half-sweeps)
 INIT_COLD = 0
 INIT_RANDOM = 1
 RECORD_WORDS = 5  # t, bond_sum, mag, accepted, unflipped
@@ -109,7 +110,9 @@ class Params:
     """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1,
     2D or 3D) or the North-East model (up-density c, 2D), the latter either by
     checkerboard half-sweeps (NORTH_EAST) or by the paper's random sub-lattice
-    algorithm (NE_TILES: side ``tile``, ``lam`` sites per iteration)."""
+    algorithm (NE_TILES: side ``tile``, ``lam`` sites per iteration).
+    NE_COUPLED moves NE sites with the Ising rates of (J, h, T) over s = 2n - 1;
+    c then only sets the initial density."""
     model: int = ISING
     dim: int = 2
     L: int = 64

@@ -2,7 +2,7 @@
 
 Plain numpy in double precision, written from the definitions:
   - energy per site e = E/N with E = -J bond_sum - h mag (Eq. 2 with a field),
-    magnetisation per site m = mag/N;
+    magnetisation per site m = mag/N (coupled NE: the same over s = 2n - 1);
   - heat capacity per site C/N = N Var(e) / T^2 (the paper's Fig. 6 compares
     <m>, <e> and C between CPU and GPU), k_B = 1;
   - susceptibility per site chi = N (<m^2> - <|m|>^2) / T (finite-lattice form);
@@ -17,17 +17,33 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ISING, Params
+from . import ISING, NE_COUPLED, Params
+
+
+def spin_sums(p: Params, records):
+    """(sum over forward bonds of s_i s_j, sum of s_i) of each record.
+
+    Ising records hold them directly.  NE records count over the occupations
+    n = (s + 1) / 2: with b = sum n_i n_j and M = sum n_i over a 2D lattice of
+    N sites and 2N forward bonds, each site in four of them,
+    sum s_i s_j = 4b - 8M + 2N and sum s_i = 2M - N."""
+    r = np.asarray(records, dtype=np.int64)
+    bond = r[:, 1].astype(np.float64)
+    mag = r[:, 2].astype(np.float64)
+    if p.model == ISING:
+        return bond, mag
+    N = float(p.nsites)
+    return 4.0 * bond - 8.0 * mag + 2.0 * N, 2.0 * mag - N
 
 
 def statistics(p: Params, records) -> dict:
-    """Means and fluctuation observables of an (n, 5) record array of an Ising run."""
-    if p.model != ISING:
-        raise ValueError("thermodynamic statistics are defined for the Ising model")
+    """Means and fluctuation observables of an (n, 5) record array of an Ising
+    run, or of a coupled NE run in its spin variables."""
+    if p.model not in (ISING, NE_COUPLED):
+        raise ValueError("thermodynamic statistics are defined for the Ising energy")
     r = np.asarray(records, dtype=np.int64)
     N = float(p.nsites)
-    bond = r[:, 1].astype(np.float64)
-    mag = r[:, 2].astype(np.float64)
+    bond, mag = spin_sums(p, r)
     e = (-p.J * bond - p.h * mag) / N
     m = mag / N
     mean_e = float(np.mean(e))

@@ -256,9 +256,19 @@ static int64_t half_sweep_ising(const or_params* p, int8_t* s, uint32_t t, uint3
     return accepted;
 }
 
+/* North-East half-sweep (Sec. 3.2): a site may change only when its north and
+ * east neighbours are up.  With J = 0 (OR_NORTH_EAST) the rates follow from
+ * the up-density c alone.  OR_NE_COUPLED keeps the Ising energy of Eq. 2 with
+ * a field, E = -J sum s_i s_j - h sum s_i over the spins s = 2n - 1, and
+ * accepts an allowed move with the Metropolis probability of that energy
+ * change: the thermodynamics of the Ising model under the NE constraint.
+ * (Eq. 3 writes the couplings with the opposite sign: its J and B are -J and
+ * -h here; J = 0, h = -1 gives the J = 0 model at the T where
+ * c = e^{-1/T} / (e^{1/T} + e^{-1/T}).) */
 static int64_t half_sweep_ne(const or_params* p, int8_t* s, uint32_t t, uint32_t colour)
 {
     const int L = p->L;
+    const int coupled = p->model == OR_NE_COUPLED;
     /* up-flip costs energy 1 (n: 0 -> 1): probability c/(1-c) capped at 1;
      * down-flip releases it: (1-c)/c capped at 1 (always, for c <= 1/2). */
     const uint64_t thr_up = or_threshold_from_prob(p->c / (1.0 - p->c));
@@ -275,7 +285,16 @@ static int64_t half_sweep_ne(const or_params* p, int8_t* s, uint32_t t, uint32_t
             int north = s[idx3(L, x, wrap(y - 1, L), 0)] & 1;
             int east = s[idx3(L, wrap(x + 1, L), y, 0)] & 1;
             if (!(north && east)) continue;          /* kinetic constraint */
-            uint64_t thr = n ? thr_down : thr_up;
+            uint64_t thr;
+            if (coupled) {
+                int south = s[idx3(L, x, wrap(y + 1, L), 0)] & 1;
+                int west = s[idx3(L, wrap(x - 1, L), y, 0)] & 1;
+                int sv = 2 * n - 1;
+                int nsum = (2 * north - 1) + (2 * east - 1) + (2 * south - 1) + (2 * west - 1);
+                thr = or_threshold(or_delta_e(p->J, p->h, sv, -sv, nsum), p->T);
+            } else {
+                thr = n ? thr_down : thr_up;
+            }
             if ((uint64_t)u < thr) {
                 s[i] = (int8_t)((n ^ 1) | 2);        /* new n, flag "has flipped" */
                 accepted += 1;
@@ -287,7 +306,7 @@ static int64_t half_sweep_ne(const or_params* p, int8_t* s, uint32_t t, uint32_t
 
 int64_t or_half_sweep(const or_params* p, int8_t* s, uint32_t t, uint32_t colour)
 {
-    if (p->model == OR_NORTH_EAST) return half_sweep_ne(p, s, t, colour);
+    if (p->model == OR_NORTH_EAST || p->model == OR_NE_COUPLED) return half_sweep_ne(p, s, t, colour);
     if (p->model != OR_ISING) return -1;     /* no colour half-sweeps */
     return half_sweep_ising(p, s, t, colour);
 }
@@ -554,11 +573,12 @@ int or_run(const or_params* p, int8_t* s, uint32_t t0, uint32_t nsweeps,
 /* The acceptance thresholds as a table, for comparison with the table the
  * GPU library exposes.  Ising layout: entry [di][nsum + z] for the spin change
  * ds = sp - s in {-2,-1,+1,+2} (di = 0..3) and nsum in [-z, z], z = 2*dim;
- * NE layout: {up-flip, down-flip}.  Returns the number of entries. */
+ * OR_NE_COUPLED uses the Ising layout (dim 2); the J = 0 NE layout is
+ * {up-flip, down-flip}.  Returns the number of entries. */
 
 int64_t or_threshold_table(const or_params* p, uint64_t* out, int64_t cap)
 {
-    if (p->model != OR_ISING) {
+    if (p->model != OR_ISING && p->model != OR_NE_COUPLED) {
         if (cap < 2) return -1;
         out[0] = or_threshold_from_prob(p->c / (1.0 - p->c));
         out[1] = or_threshold_from_prob((1.0 - p->c) / p->c);

@@ -17,6 +17,7 @@ extern "C" {
 #define OR_NORTH_EAST 1
 #define OR_NE_TILES 2   /* North-East model, paper's random sub-lattice algorithm */
 #define OR_NE_BALANCED 3 /* its balanced variant: red, then white sites */
+#define OR_NE_COUPLED 4  /* NE constraint on the Ising energy (J, h, T): Sec. 3.2, J != 0 */
 #define OR_INIT_COLD 0
 #define OR_INIT_RANDOM 1
 #define OR_TAG_SWEEP 0u
@@ -26,14 +27,14 @@ extern "C" {
 #define OR_RECORD_WORDS 5
 
 typedef struct {
-    int32_t model;   /* OR_ISING, OR_NORTH_EAST, OR_NE_TILES or OR_NE_BALANCED */
+    int32_t model;   /* OR_ISING, OR_NORTH_EAST, OR_NE_TILES, OR_NE_BALANCED, OR_NE_COUPLED */
     int32_t dim;     /* 2 or 3 (NE: 2) */
     int32_t L;       /* even */
     int32_t two_s;   /* 1: s in {-1,+1}; 2: s in {-1,0,+1} */
     int32_t init;    /* OR_INIT_COLD / OR_INIT_RANDOM (Ising) */
     int32_t pad;
-    double J, h, T;  /* Ising */
-    double c;        /* NE up-density, 0 < c < 1 */
+    double J, h, T;  /* Ising and OR_NE_COUPLED */
+    double c;        /* NE up-density, 0 < c < 1 (OR_NE_COUPLED: initial state only) */
     uint64_t seed;
     int32_t tile;    /* OR_NE_TILES: side B of the square sub-lattices */
     int32_t lambda;  /* OR_NE_TILES: sites updated together per iteration */
