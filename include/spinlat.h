@@ -10,6 +10,11 @@
  *   - North-East facilitated model, Sec. 3.2 Eq. 3 with J = 0: occupation
  *     n in {0,1}, a site may change only when its north and east neighbours
  *     are up; equilibrium up-density c;
+ *   - the same constraint on the Ising energy (Sec. 3.2, J != 0; model
+ *     SL_NE_COUPLED): an allowed move n -> 1-n is accepted with the Metropolis
+ *     probability of E = -J sum s_i s_j - h sum s_i over s = 2n - 1 (Eq. 3
+ *     writes the couplings with the opposite sign: its J and B are -J and -h
+ *     here), checkerboard half-sweeps, c only sets the initial density;
  *   - Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.1), evaluated as an
  *     integer compare of a 32-bit Philox4x32-10 word against a threshold
  *     table computed on the host in double precision;
@@ -39,7 +44,9 @@
  *   Spin-1/2: accept s -> -s iff word < thr.  Spin-1: word j=0 accepts,
  *   word j=1 picks the proposal (lower of the two other values iff < 2^31).
  *   NE: word decides up-flips (thr = floor(min(1, c/(1-c)) 2^32)) and
- *   down-flips (floor(min(1, (1-c)/c) 2^32)).
+ *   down-flips (floor(min(1, (1-c)/c) 2^32)).  SL_NE_COUPLED: the spin-1/2
+ *   Ising threshold of the move s -> -s, s = 2n - 1, nsum over the four
+ *   neighbours' 2n - 1; the move needs the north and east neighbours up.
  *   NE sub-lattices: attempt a = j*lambda + l (thread l, iteration j) on
  *   sub-lattice tau = (y0/B)*(L/B) + x0/B in launch m (m = 2t, then 2t+1) uses
  *   words 2(a mod 2) and 2(a mod 2)+1 of Philox4x32-10(key = seed,
@@ -61,7 +68,8 @@
  * (NE: sum_i n_i, bond_sum over n), accepted = moves accepted in that sweep
  * (NE sub-lattices: per iteration, the number of sites that changed),
  * unflipped = NE sites not flipped since the persistence origin (-1 for
- * Ising)}.  Energy: Ising E = -J bond_sum - h mag.
+ * Ising)}.  Energy: Ising E = -J bond_sum - h mag; SL_NE_COUPLED the same over
+ * s = 2n - 1, i.e. E = -J (4 bond_sum - 8 mag + 2N) - h (2 mag - N).
  *
  * Ownership: the caller owns the device buffer (sl_query_bytes bytes, 256-byte
  * aligned) and the HIP stream; the handle borrows both and must be destroyed
@@ -99,8 +107,10 @@ typedef enum sl_model {
     SL_ISING = 0,
     SL_NORTH_EAST = 1,    /* NE model, checkerboard half-sweeps */
     SL_NE_SUBLATTICE = 2, /* NE model, random sub-lattice algorithm (Sec. 3.2) */
-    SL_NE_SUBLATTICE_BALANCED = 3 /* its balanced variant: colour 0 then colour 1 sites
-                                     per iteration, four launches per sweep */
+    SL_NE_SUBLATTICE_BALANCED = 3, /* its balanced variant: colour 0 then colour 1 sites
+                                      per iteration, four launches per sweep */
+    SL_NE_COUPLED = 4 /* NE constraint with the Ising rates of (J, h, T), checkerboard
+                         half-sweeps; SL_MODE_SIMPLE and SL_MODE_RESIDENT only */
 } sl_model;
 
 typedef enum sl_init {
@@ -116,8 +126,9 @@ typedef struct sl_params {
     int32_t L;                /* linear size, even, >= 2; kernels need L % 8 == 0 */
     int32_t two_s;            /* 1: s in {-1,+1}; 2: s in {-1,0,+1} */
     int32_t init;             /* sl_init */
-    double J, h, T;           /* Ising coupling, field, temperature (T > 0, may be +inf) */
-    double c;                 /* NE up-density, 0 < c < 1 */
+    double J, h, T;           /* Ising (and SL_NE_COUPLED) coupling, field, temperature
+                                 (T > 0, may be +inf) */
+    double c;                 /* NE up-density, 0 < c < 1 (SL_NE_COUPLED: initial only) */
     uint64_t seed;            /* Philox key */
     uint64_t t0;              /* index of the first sweep (resume), < 2^32 */
     uint64_t record_capacity; /* records held on the device between sl_measure calls, >= 1 */
@@ -166,8 +177,9 @@ typedef struct sl_launch {
  * Host-only, pure.  SL_E_INVALID / SL_E_UNSUPPORTED as sl_create_lattice. */
 sl_status sl_query_bytes(const sl_params* params, size_t* device_bytes);
 
-/* Threshold table the kernels use (host-only, pure).  Ising: 4*(4*dim+1)
- * entries, [di][nsum + 2*dim] for s'-s = {-2,-1,+1,+2}[di]; NE: {up, down}.
+/* Threshold table the kernels use (host-only, pure).  Ising and
+ * SL_NE_COUPLED: 4*(4*dim+1) entries, [di][nsum + 2*dim] for
+ * s'-s = {-2,-1,+1,+2}[di]; the J = 0 NE models: {up, down}.
  * Each entry is in [0, 2^32]. */
 sl_status sl_threshold_table(const sl_params* params, uint64_t* out, size_t cap,
                              size_t* n_out);
@@ -182,7 +194,8 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
  * the schedule does not fit the shape: HALF/FUSED need the colour row to split
  * into row groups of <= 64 lanes or a multiple of 64 lanes up to 1024, and for
  * spin-1/2 every threshold >= 1; the window modes take any shape).  NE
- * sub-lattice lattices have one schedule and accept only SL_MODE_AUTO. */
+ * sub-lattice lattices have one schedule and accept only SL_MODE_AUTO;
+ * SL_NE_COUPLED lattices take SL_MODE_SIMPLE and SL_MODE_RESIDENT. */
 sl_status sl_set_launch(sl_lattice* lat, const sl_launch* launch);
 sl_status sl_get_launch(const sl_lattice* lat, sl_launch* launch);
 
@@ -212,7 +225,9 @@ sl_status sl_destroy(sl_lattice* lat);
 /* Observables of n records (host-only, pure, double precision): Ising
  * E = -J bond_sum - h mag (Eq. 2 with a field), M = mag, P = NaN; NE (J = 0,
  * one unit of energy per up site, Eq. 3 read with n in {0,1}): E = mag,
- * M = mag, P = unflipped / L^dim (persistence).  Any output may be NULL. */
+ * M = mag, P = unflipped / L^dim (persistence); SL_NE_COUPLED: E the Ising
+ * energy over s = 2n - 1 (see Records), M = mag, P as NE.  Any output may be
+ * NULL. */
 sl_status sl_record_observables(const sl_params* params, const sl_record* records, size_t n,
                                 double* E, double* M, double* P);
 
@@ -304,9 +319,10 @@ typedef struct sl_stats {
     double binder;         /* 1 - <m^4> / (3 <m^2>^2); NaN if <m^2> = 0 */
 } sl_stats;
 
-/* Means over records[0..n) of an Ising run (host-only, pure, double precision;
- * the caller leaves out the records before equilibrium).  SL_E_INVALID for
- * n == 0 or NE parameters. */
+/* Means over records[0..n) of an Ising run, or of an SL_NE_COUPLED run in its
+ * spin variables s = 2n - 1 (host-only, pure, double precision; the caller
+ * leaves out the records before equilibrium).  SL_E_INVALID for n == 0 or the
+ * J = 0 NE models. */
 sl_status sl_record_statistics(const sl_params* params, const sl_record* records, size_t n,
                                sl_stats* out);
 

@@ -196,6 +196,8 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     if (is_sub_lattice(p->model))
         return fail(SL_E_UNSUPPORTED, "batched jobs use the checkerboard sweep; the NE "
                                       "sub-lattice algorithm runs as a single lattice");
+    if (p->model == SL_NE_COUPLED)
+        return fail(SL_E_UNSUPPORTED, "coupled NE lattices run as single lattices");
     *foot = job_foot(p, cfg->record_capacity);
     *table_n = build_table(p, table);
     bool lut32 = true;

@@ -169,12 +169,13 @@ __global__ void __launch_bounds__(kBlock) k_fold(unsigned long long* acc, int64_
 // Direct update of one 4-site word gi of colour c: the neighbours are read
 // straight from the other colour array (global memory, or LDS in the resident
 // kernel).  With update == 0 only the observables of the current state are
-// accumulated (record r_0).
+// accumulated (record r_0).  `coupled` (NE only) takes the Ising rates of the
+// spin-1/2 table instead of the two J = 0 thresholds.
 template <int KIND, int DIM>
 __device__ __forceinline__ void simple_word(uint8_t* own, const int8_t* oth, const Geom& g, uint32_t c,
                                             uint64_t gi, uint32_t t, int update, const PhiloxKey& ks,
-                                            const uint64_t* lut, int32_t& q_bond, int32_t& q_mag,
-                                            int32_t& q_acc, int32_t& q_unfl)
+                                            const uint64_t* lut, bool coupled, int32_t& q_bond,
+                                            int32_t& q_mag, int32_t& q_acc, int32_t& q_unfl)
 {
     {
         const bool upd = update != 0;
@@ -210,14 +211,17 @@ __device__ __forceinline__ void simple_word(uint8_t* own, const int8_t* oth, con
             if (KIND == KIND_NE) {
                 const int north = oth[r_ym * g.Lh + kk];
                 const int east = oth[row * g.Lh + (p ? kside : kk)];
-                nv = upd ? move_ne(sv, north, east, wa.w[b], lut[0], lut[1]) : sv;
+                int south = 0, west = 0;
+                if (c == 1 || coupled) {
+                    south = oth[r_yp * g.Lh + kk];
+                    west = oth[row * g.Lh + (p ? kk : kside)];
+                }
+                if (!upd) nv = sv;
+                else if (coupled) nv = move_ne_coupled(sv, north, east, south, west, wa.w[b], lut);
+                else nv = move_ne(sv, north, east, wa.w[b], lut[0], lut[1]);
                 q_mag += nv & 1;
                 q_unfl += (nv & 2) ? 0 : 1;
-                if (c == 1) {
-                    const int south = oth[r_yp * g.Lh + kk];
-                    const int west = oth[row * g.Lh + (p ? kk : kside)];
-                    q_bond += (nv & 1) * ((north & 1) + (east & 1) + (south & 1) + (west & 1));
-                }
+                if (c == 1) q_bond += (nv & 1) * ((north & 1) + (east & 1) + (south & 1) + (west & 1));
             } else {
                 int nsum = oth[row * g.Lh + kk] + oth[row * g.Lh + kside] + oth[r_ym * g.Lh + kk] +
                            oth[r_yp * g.Lh + kk];
@@ -254,8 +258,8 @@ __global__ void __launch_bounds__(kBlock) k_simple_half(SweepArgs a)
     if (gi < ngroups) {
         const PhiloxKey ks = philox_schedule(a.key0, a.key1);
         simple_word<KIND, DIM>(a.col[a.colour], reinterpret_cast<const int8_t*>(a.col[a.colour ^ 1u]),
-                               a.g, a.colour, gi, a.t, a.update, ks, lut, q_bond, q_mag, q_acc,
-                               q_unfl);
+                               a.g, a.colour, gi, a.t, a.update, ks, lut, KIND == KIND_NE && a.lut_n > 2,
+                               q_bond, q_mag, q_acc, q_unfl);
     }
     block_accumulate(q_bond, q_mag, q_acc, q_unfl, a.acc);
 }
@@ -280,6 +284,7 @@ __global__ void __launch_bounds__(kResidentBlock) k_resident(SweepArgs a, uint32
     for (int i = threadIdx.x; i < a.lut_n; i += kResidentBlock) lut[i] = a.lut[i];
     __syncthreads();
     const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+    const bool coupled = KIND == KIND_NE && a.lut_n > 2;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         int32_t q_bond = 0, q_mag = 0, q_acc = 0, q_unfl = 0;
 #pragma unroll
@@ -287,8 +292,8 @@ __global__ void __launch_bounds__(kResidentBlock) k_resident(SweepArgs a, uint32
             uint8_t* own = sm + c * nh;
             const int8_t* oth = reinterpret_cast<const int8_t*>(sm + (c ^ 1u) * nh);
             for (uint32_t gi = threadIdx.x; gi < nwords; gi += kResidentBlock)
-                simple_word<KIND, DIM>(own, oth, a.g, c, gi, a.t + s, 1, ks, lut, q_bond, q_mag, q_acc,
-                                       q_unfl);
+                simple_word<KIND, DIM>(own, oth, a.g, c, gi, a.t + s, 1, ks, lut, coupled, q_bond, q_mag,
+                                       q_acc, q_unfl);
             __syncthreads();
         }
         block_accumulate(q_bond, q_mag, q_acc, q_unfl, a.acc + (uint64_t)s * kSlotWords);

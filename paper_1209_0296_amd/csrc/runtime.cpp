@@ -66,7 +66,7 @@ sl_status validate(const sl_params* p)
     if (p->abi_version != SL_ABI_VERSION)
         return fail(SL_E_INVALID, "abi_version %u != %u", p->abi_version, SL_ABI_VERSION);
     if (p->model != SL_ISING && p->model != SL_NORTH_EAST && p->model != SL_NE_SUBLATTICE &&
-        p->model != SL_NE_SUBLATTICE_BALANCED)
+        p->model != SL_NE_SUBLATTICE_BALANCED && p->model != SL_NE_COUPLED)
         return fail(SL_E_INVALID, "unknown model %d", p->model);
     if (p->dim != 2 && p->dim != 3) return fail(SL_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
     if (p->L < 2 || (p->L & 1))
@@ -78,11 +78,12 @@ sl_status validate(const sl_params* p)
         return fail(SL_E_INVALID, "unknown init %d", p->init);
     if (p->init == SL_INIT_BUFFER && !p->init_spins)
         return fail(SL_E_INVALID, "SL_INIT_BUFFER needs init_spins");
-    if (p->model == SL_ISING) {
+    if (p->model == SL_ISING || p->model == SL_NE_COUPLED) {
         if (!(p->T > 0.0)) return fail(SL_E_INVALID, "T must be > 0 (got %g)", p->T);
         if (std::isnan(p->J) || std::isnan(p->h) || std::isinf(p->J) || std::isinf(p->h))
             return fail(SL_E_INVALID, "J and h must be finite");
-    } else {
+    }
+    if (p->model != SL_ISING) {
         if (p->dim != 2) return fail(SL_E_INVALID, "the North-East model is two-dimensional");
         if (p->two_s != 1) return fail(SL_E_INVALID, "the North-East model has binary sites");
         if (!(p->c > 0.0 && p->c < 1.0))
@@ -150,7 +151,7 @@ uint64_t thr_from_energy(double dE, double T)
 
 size_t build_table(const sl_params* p, uint64_t* out)
 {
-    if (p->model != SL_ISING) {
+    if (p->model != SL_ISING && p->model != SL_NE_COUPLED) {
         out[0] = thr_from_prob(p->c / (1.0 - p->c));  // up-flip: energy +1
         out[1] = thr_from_prob((1.0 - p->c) / p->c);  // down-flip
         return 2;
@@ -170,6 +171,30 @@ size_t build_table(const sl_params* p, uint64_t* out)
 }  // namespace spinlat
 
 using namespace spinlat::host;
+
+namespace {
+
+// NE records count over the occupations n = (s + 1) / 2.  On a 2D lattice of
+// N sites and 2N forward bonds, each site in four of them:
+// sum s_i s_j = 4 bond - 8 mag + 2N and sum s_i = 2 mag - N.
+void spin_sums(const sl_record& r, double nsites, double& bond, double& mag)
+{
+    bond = 4.0 * (double)r.bond_sum - 8.0 * (double)r.mag + 2.0 * nsites;
+    mag = 2.0 * (double)r.mag - nsites;
+}
+
+// (bond, mag) in spin variables for the statistics of either energy model.
+void stat_sums(const sl_params* p, const sl_record& r, double nsites, double& bond, double& mag)
+{
+    if (p->model == SL_NE_COUPLED) {
+        spin_sums(r, nsites, bond, mag);
+    } else {
+        bond = (double)r.bond_sum;
+        mag = (double)r.mag;
+    }
+}
+
+}  // namespace
 
 struct sl_lattice {
     sl_params params;
@@ -255,6 +280,11 @@ sl_launch auto_launch(const sl_lattice* h)
         r.mode = SL_MODE_RESIDENT;
         return r;
     }
+    if (h->params.model == SL_NE_COUPLED) {  // the streaming kernels take the J = 0 rates only
+        sl_launch r{};
+        r.mode = SL_MODE_SIMPLE;
+        return r;
+    }
     const int L = h->params.L;
     const bool fused = h->params.dim == 2;
     const bool half_spin = h->kind == KIND_ISING_HALF;
@@ -301,6 +331,8 @@ sl_status check_launch(const sl_lattice* h, sl_launch* l)
     }
     const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
                     0u, h->lay.nh};
+    if (h->params.model == SL_NE_COUPLED && l->mode != SL_MODE_SIMPLE && l->mode != SL_MODE_RESIDENT)
+        return fail(SL_E_UNSUPPORTED, "coupled NE lattices run SL_MODE_SIMPLE or SL_MODE_RESIDENT");
     switch (l->mode) {
         case SL_MODE_SIMPLE:
             return SL_OK;
@@ -679,6 +711,11 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
         if (params->model == SL_ISING) {
             if (E) E[i] = -params->J * (double)r.bond_sum - params->h * (double)r.mag;
             if (P) P[i] = std::nan("");
+        } else if (params->model == SL_NE_COUPLED) {
+            double bond, mag;
+            spin_sums(r, nsites, bond, mag);
+            if (E) E[i] = -params->J * bond - params->h * mag;
+            if (P) P[i] = (double)r.unflipped / nsites;
         } else {
             if (E) E[i] = (double)r.mag;
             if (P) P[i] = (double)r.unflipped / nsites;
@@ -693,15 +730,17 @@ sl_status sl_record_statistics(const sl_params* params, const sl_record* records
 {
     sl_status st = validate(params);
     if (st != SL_OK && st != SL_E_UNSUPPORTED) return st;
-    if (params->model != SL_ISING)
-        return fail(SL_E_INVALID, "thermodynamic statistics are defined for the Ising model");
+    if (params->model != SL_ISING && params->model != SL_NE_COUPLED)
+        return fail(SL_E_INVALID, "thermodynamic statistics are defined for the Ising energy");
     if (n == 0 || !records || !out) return fail(SL_E_INVALID, "need n >= 1 records and an output");
     const double N = (double)layout_of(params).nsites;
     const double inv_n = 1.0 / (double)n;
     double se = 0.0, sm = 0.0, sma = 0.0, sm2 = 0.0, sm4 = 0.0;
     for (size_t i = 0; i < n; ++i) {
-        const double e = (-params->J * (double)records[i].bond_sum - params->h * (double)records[i].mag) / N;
-        const double m = (double)records[i].mag / N;
+        double bond, mag;
+        stat_sums(params, records[i], N, bond, mag);
+        const double e = (-params->J * bond - params->h * mag) / N;
+        const double m = mag / N;
         se += e;
         sm += m;
         sma += std::fabs(m);
@@ -711,7 +750,9 @@ sl_status sl_record_statistics(const sl_params* params, const sl_record* records
     const double mean_e = se * inv_n;
     double sv = 0.0;  // second pass: variance of e
     for (size_t i = 0; i < n; ++i) {
-        const double e = (-params->J * (double)records[i].bond_sum - params->h * (double)records[i].mag) / N;
+        double bond, mag;
+        stat_sums(params, records[i], N, bond, mag);
+        const double e = (-params->J * bond - params->h * mag) / N;
         sv += (e - mean_e) * (e - mean_e);
     }
     sl_stats r{};

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspinlat.so")
 
 ABI_VERSION = 2
-ISING, NORTH_EAST, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED = 0, 1, 2, 3
+ISING, NORTH_EAST, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, NE_COUPLED = 0, 1, 2, 3, 4
 INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
 MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
 MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT = 4, 5, 6
@@ -150,7 +150,9 @@ class Params:
     """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1; 2D or
     3D) or the North-East model (up-density c; 2D), by checkerboard half-sweeps
     (NORTH_EAST) or by the random sub-lattice algorithm of Sec. 3.2
-    (NE_SUBLATTICE: side ``ne_side``, ``ne_lambda`` sites per iteration)."""
+    (NE_SUBLATTICE: side ``ne_side``, ``ne_lambda`` sites per iteration).
+    NE_COUPLED moves NE sites with the Ising rates of (J, h, T) over s = 2n - 1
+    (Sec. 3.2, J != 0); c then only sets the initial density."""
     model: int = ISING
     dim: int = 2
     L: int = 64
@@ -314,8 +316,9 @@ class Lattice:
 
 
 def record_statistics(p: Params, records) -> dict:
-    """Means, heat capacity, susceptibility and Binder cumulant of Ising records
-    (structured records or an (n, 5) int64 array), computed by the library."""
+    """Means, heat capacity, susceptibility and Binder cumulant of Ising records,
+    or of coupled NE records in their spin variables (structured records or an
+    (n, 5) int64 array), computed by the library."""
     recs = np.ascontiguousarray(records)
     if recs.dtype != RECORD_DTYPE:
         a = np.asarray(recs, dtype=np.int64)

@@ -10,7 +10,7 @@ import paper_1209_0296_amd as S
 
 def oracle_params(sp: S.Params) -> O.Params:
     model = {S.ISING: O.ISING, S.NORTH_EAST: O.NORTH_EAST, S.NE_SUBLATTICE: O.NE_TILES,
-             S.NE_SUBLATTICE_BALANCED: O.NE_BALANCED}[sp.model]
+             S.NE_SUBLATTICE_BALANCED: O.NE_BALANCED, S.NE_COUPLED: O.NE_COUPLED}[sp.model]
     return O.Params(model=model, dim=sp.dim, L=sp.L, two_s=sp.two_s,
                     init=O.INIT_COLD if sp.init == S.INIT_COLD else O.INIT_RANDOM,
                     J=sp.J, h=sp.h, T=sp.T, c=sp.c, seed=sp.seed,

@@ -54,6 +54,10 @@ def _status(p):
     (dict(model=3, L=64, ne_side=8, ne_lambda=16), 1), (dict(model=3, L=64, ne_side=8, ne_lambda=3), 1),
     (dict(model=3, L=96, ne_side=12, ne_lambda=2), 2), (dict(model=3, t0=2 ** 30), 6),
     (dict(model=3, init=S.INIT_COLD), 1),
+    # NE with the Ising coupling
+    (dict(model=4, T=0.0), 1), (dict(model=4, J=float("nan")), 1), (dict(model=4, h=float("inf")), 1),
+    (dict(model=4, dim=3), 1), (dict(model=4, c=0.0), 1), (dict(model=4, init=S.INIT_COLD), 1),
+    (dict(model=4, L=12), 2),
 ])
 def test_invalid_parameters_rejected(kw, code):
     st, _ = _status(S.Params(**kw))
@@ -84,6 +88,7 @@ def test_infinite_temperature_allowed():
     dict(T=1.1, J=-1.0, h=0.2), dict(dim=3, T=4.5115), dict(two_s=2, T=1.6935),
     dict(dim=3, two_s=2, T=3.19, h=-0.5), dict(model=1, c=0.05), dict(model=1, c=0.1),
     dict(model=1, c=0.2), dict(model=1, c=0.7), dict(model=2, c=0.42), dict(model=2, c=0.8),
+    dict(model=4, J=1.0, h=0.3, T=2.0), dict(model=4, J=-0.5, T=1.0), dict(model=4, J=0.0, h=-1.0, T=0.9),
 ])
 def test_threshold_table_equals_oracle(kw):
     p = S.Params(**kw)
@@ -105,6 +110,16 @@ def test_record_observables():
     recs["unflipped"] = [64, 16]
     assert S.lib().sl_record_observables(ctypes.byref(q.c_struct()), recs.ctypes.data, 2,
                                          E.ctypes.data, M.ctypes.data, P.ctypes.data) == 0
+    np.testing.assert_array_equal(P, [1.0, 0.25])
+    # coupled NE: the Ising energy of s = 2n - 1 from the occupation counts
+    r = S.Params(model=S.NE_COUPLED, L=8, J=1.5, h=0.25, c=0.2)
+    assert S.lib().sl_record_observables(ctypes.byref(r.c_struct()), recs.ctypes.data, 2,
+                                         E.ctypes.data, M.ctypes.data, P.ctypes.data) == 0
+    N = 64.0
+    for i in range(2):
+        b, m = float(recs["bond_sum"][i]), float(recs["mag"][i])
+        assert E[i] == -1.5 * (4 * b - 8 * m + 2 * N) - 0.25 * (2 * m - N)
+    np.testing.assert_array_equal(M, [10, -4])
     np.testing.assert_array_equal(P, [1.0, 0.25])
 
 
@@ -138,8 +153,9 @@ def test_balanced_shapes_accepted(B, lam):
 def test_sub_lattice_jobs_not_batched():
     cfg = S.batch_config(max_jobs=4, record_capacity=8)
     n = ctypes.c_size_t()
-    cp = S.Params(model=S.NE_SUBLATTICE, L=64).c_struct()
-    assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
+    for model in (S.NE_SUBLATTICE, S.NE_COUPLED):
+        cp = S.Params(model=model, L=64).c_struct()
+        assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
 
 
 def _records_from(rec):
@@ -150,7 +166,8 @@ def _records_from(rec):
 
 
 @pytest.mark.parametrize("kw", [dict(L=64, T=2.269), dict(L=64, T=2.6, h=0.1, J=0.8),
-                                dict(dim=3, L=16, T=4.5)])
+                                dict(dim=3, L=16, T=4.5),
+                                dict(model=4, L=16, J=1.0, h=0.1, T=2.5, c=0.6)])
 def test_record_statistics_equal_oracle(kw):
     """sl_record_statistics against the oracle's statistics on oracle records."""
     from oracle import observables as OB
