@@ -165,6 +165,19 @@ __global__ void __launch_bounds__(kBlock) k_fold(unsigned long long* acc, int64_
     o[4] = ising ? -1 : sum[3];
 }
 
+// North-East constraint on the Ising energy (Sec. 3.2 with J != 0): an
+// allowed move n -> 1 - n is the spin-1/2 move s -> -s of s = 2n - 1, with
+// nsum over the four neighbours' 2n - 1 (spin-1/2 table, z = 4).
+__device__ __forceinline__ int move_ne_coupled(int byte, int north, int east, int south, int west,
+                                               uint32_t u, const uint64_t* lut)
+{
+    if (!((north & east) & 1)) return byte;
+    const int n = byte & 1;
+    const int s = 2 * n - 1;
+    const int nsum = 2 * ((north & 1) + (east & 1) + (south & 1) + (west & 1)) - 4;
+    return move_ising_half(s, nsum, u, lut, 4) != s ? ((n ^ 1) | 2) : byte;
+}
+
 // ---------------------------------------------------------------------------
 // Direct update of one 4-site word gi of colour c: the neighbours are read
 // straight from the other colour array (global memory, or LDS in the resident

@@ -8,7 +8,6 @@
 // North-East model (Sec. 3.2, Eq. 3, J = 0): the site may change only if its
 // north and east neighbours are both up; an up-flip uses thr_up, a down-flip
 // thr_down (table entries 0 and 1); bit 1 of the byte records "has flipped".
-// The coupled variant keeps the constraint and takes the Ising rates.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -49,19 +48,6 @@ __device__ __forceinline__ int move_ne(int byte, int north, int east, uint32_t u
     if (!((north & east) & 1)) return byte;
     const uint64_t thr = n ? thr_down : thr_up;
     return ((uint64_t)u < thr) ? ((n ^ 1) | 2) : byte;
-}
-
-// North-East constraint on the Ising energy (Sec. 3.2 with J != 0): an
-// allowed move n -> 1 - n is the spin-1/2 move s -> -s of s = 2n - 1, with
-// nsum over the four neighbours' 2n - 1 (spin-1/2 table, z = 4).
-__device__ __forceinline__ int move_ne_coupled(int byte, int north, int east, int south, int west,
-                                               uint32_t u, const uint64_t* lut)
-{
-    if (!((north & east) & 1)) return byte;
-    const int n = byte & 1;
-    const int s = 2 * n - 1;
-    const int nsum = 2 * ((north & 1) + (east & 1) + (south & 1) + (west & 1)) - 4;
-    return move_ising_half(s, nsum, u, lut, 4) != s ? ((n ^ 1) | 2) : byte;
 }
 
 // Sum four per-thread int32 partials over the workgroup and add them to one
