@@ -225,7 +225,7 @@ def main():
     secondary = []
     if not args.no_secondary:
         for key in ("ising2d_L64", "ising2d_L32768", "ising3d_L256_s12", "ising3d_L256_s1",
-                    "ne2d_L4096", "ne2d_sub_L4096", "ne2d_subbal_L4096"):
+                    "ne2d_L4096", "ne2d_sub_L4096", "ne2d_subbal_L4096", "ne2d_coupled_L4096"):
             r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)

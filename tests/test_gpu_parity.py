@@ -272,14 +272,15 @@ def test_record_ring_errors():
 # on all host threads: the whole lattice and every record.
 
 @pytest.mark.parametrize("name,nsweeps", [("ising2d_L8192", 3), ("ising3d_L256_s12", 4),
-                                          ("ising3d_L256_s1", 3), ("ne2d_L4096", 6)])
+                                          ("ising3d_L256_s1", 3), ("ne2d_L4096", 6),
+                                          ("ne2d_coupled_L4096", 4)])
 def test_benchmarked_sizes(name, nsweeps):
     from workloads import CONFIGS
 
     cfg = CONFIGS[name]
     sp = S.Params(model=cfg["model"], dim=cfg["dim"], L=cfg["L"], two_s=cfg["two_s"],
-                  T=cfg.get("T", 1.0), c=cfg.get("c", 0.1), seed=cfg["seed"], init=cfg["init"],
-                  record_capacity=16)
+                  J=cfg.get("J", 1.0), h=cfg.get("h", 0.0), T=cfg.get("T", 1.0),
+                  c=cfg.get("c", 0.1), seed=cfg["seed"], init=cfg["init"], record_capacity=16)
     _check(sp, nsweeps, launch=AUTO, nthreads=16)
 
 

@@ -16,7 +16,8 @@ import numpy as np
 TC_2D = 2.0 / math.log(1.0 + math.sqrt(2.0))  # exact 2D Ising critical temperature
 
 # name -> keyword arguments of Params (model 0 = Ising, 1 = North-East by
-# checkerboard, 2 = North-East by random sub-lattices, 3 = its balanced variant)
+# checkerboard, 2 = North-East by random sub-lattices, 3 = its balanced variant,
+# 4 = North-East constraint on the Ising energy)
 CONFIGS = {
     # 64x64, cold start, T = 2.269, 1000 sweeps, records every sweep
     "ising2d_L64": dict(model=0, dim=2, L=64, two_s=1, J=1.0, h=0.0, T=2.269, seed=1, init=0,
@@ -43,6 +44,9 @@ CONFIGS = {
     # its balanced variant (colour 0, then colour 1 sites; four launches per sweep)
     "ne2d_subbal_L4096": dict(model=3, dim=2, L=4096, two_s=1, c=0.1, seed=1, init=1,
                               sweeps=100000, ne_side=32, ne_lambda=16),
+    # the NE constraint on the Ising energy (J = 1, h = 0, T = 3), Bernoulli(1/2) start
+    "ne2d_coupled_L4096": dict(model=4, dim=2, L=4096, two_s=1, J=1.0, h=0.0, T=3.0, c=0.5,
+                               seed=1, init=1, sweeps=100000),
 }
 
 # critical-temperature estimates used only to place temperatures (results do
