@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
     __shared__ RowLuts lut;
     __shared__ uint32_t xch[2][16][2];
     uint64_t thr_up, thr_down;
-    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down);
+    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down, a.lut_n);
     __syncthreads();
 
     Obs o = {0, 0, 0, 0, 0};
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(1024) k_row_fused(SweepArgs a, RowGeom rg, con
     __shared__ RowLuts lut;
     __shared__ uint32_t xch[2][16][4];
     uint64_t thr_up, thr_down;
-    build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down);
+    build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down, a.lut_n);
     __syncthreads();
 
     Obs o = {0, 0, 0, 0, 0};

@@ -140,13 +140,19 @@ struct RowLuts {
     uint64_t e[3 * 2 * 13];  // spin-1 entries; spin-1/2 uses the first words as u32
 };
 
+// NE lattices with the Ising coupling (a table of more than the two J = 0
+// thresholds) get the spin-1/2 table, and thr_up = thr_down = kNeCoupled,
+// which no J = 0 threshold (<= 2^32) can equal.
+constexpr uint64_t kNeCoupled = ~0ull;
+
 template <int KIND, int DIM>
 __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* table, uint64_t& thr_up,
-                                               uint64_t& thr_down)
+                                               uint64_t& thr_down, int table_n = 2)
 {
     constexpr int z = 2 * DIM;
+    const bool coupled = KIND == KIND_NE && table_n > 2;
     for (int t = threadIdx.x; t < 6 * (2 * z + 1); t += blockDim.x) {
-        if (KIND == KIND_ISING_HALF) {
+        if (KIND == KIND_ISING_HALF || coupled) {
             if (t < 2 * (z + 1)) {
                 // entry nd + sneg*(z+1): nd neighbours at -1, sneg = (s == -1)
                 const int sneg = t / (z + 1), nd = t % (z + 1);
@@ -168,8 +174,8 @@ __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* tab
             lut.e[t] = thr | ((uint64_t)(uint32_t)(sp + 1) << 40);
         }
     }
-    thr_up = table[0];
-    thr_down = table[1];
+    thr_up = coupled ? kNeCoupled : table[0];
+    thr_down = coupled ? kNeCoupled : table[1];
 }
 
 struct Obs {
@@ -240,6 +246,30 @@ __device__ __forceinline__ uint32_t one_word(uint32_t own, uint32_t S, const Wor
         out |= ((n1 - 1u) & 0xFFu) << (8 * b);
     }
     return out;
+}
+
+// NE constraint on the Ising energy (Sec. 3.2 with J != 0): a site whose north
+// and east neighbours are up takes the spin-1/2 move of s = 2n - 1.  S holds
+// the number of up neighbours per byte, so the table entry nd + sneg*5 (nd
+// neighbours down, sneg = 1 - n) is 9 - S - 5n, with no borrow between bytes.
+__device__ __forceinline__ uint32_t ne_coupled_word(uint32_t own, uint32_t north, uint32_t east, uint32_t S,
+                                                    uint32_t g, uint32_t colour, uint32_t t,
+                                                    const PhiloxKey& ks, const RowLuts& lut)
+{
+    const uint32_t n = own & 0x01010101u;
+    const uint32_t allowed = north & east;
+    uint32_t f = 0;
+    if (__builtin_amdgcn_ballot_w64(allowed != 0u) != 0ull) {
+        const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
+        const uint32_t idx = 0x09090909u - S - n * 5u;
+        const uint32_t* thr_m1 = reinterpret_cast<const uint32_t*>(lut.e);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t bit = 1u << (8 * b);
+            if ((allowed & bit) && w.w[b] <= thr_m1[(idx >> (8 * b)) & 0xFFu]) f |= bit;
+        }
+    }
+    return (own ^ f) | (f << 1);
 }
 
 __device__ __forceinline__ uint32_t ne_word(uint32_t own, uint32_t north, uint32_t east, uint32_t g,
@@ -315,7 +345,11 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
             // north = row y-1; east = site x+1 (side word when p = 1)
             const uint32_t east = P ? side[d] : same.w[d];
             const uint32_t west = P ? same.w[d] : side[d];
-            out.w[d] = ne_word(own.w[d], up.w[d], east, g, colour, t, ks, thr_up, thr_down);
+            if (thr_up == kNeCoupled)
+                out.w[d] = ne_coupled_word(own.w[d], up.w[d], east, up.w[d] + down.w[d] + east + west, g,
+                                           colour, t, ks, lut);
+            else
+                out.w[d] = ne_word(own.w[d], up.w[d], east, g, colour, t, ks, thr_up, thr_down);
             if (count) {
                 const uint32_t n = out.w[d] & 0x01010101u;
                 o.acc += __builtin_popcount((own.w[d] ^ out.w[d]) & 0x01010101u);

@@ -280,7 +280,8 @@ sl_launch auto_launch(const sl_lattice* h)
         r.mode = SL_MODE_RESIDENT;
         return r;
     }
-    if (h->params.model == SL_NE_COUPLED) {  // the streaming kernels take the J = 0 rates only
+    const bool coupled = h->params.model == SL_NE_COUPLED;
+    if (coupled && !lut32_ok(h)) {  // the row kernels keep "word <= thr - 1" in 32 bits
         sl_launch r{};
         r.mode = SL_MODE_SIMPLE;
         return r;
@@ -316,7 +317,7 @@ sl_launch auto_launch(const sl_lattice* h)
             l.tile_words = D;
             return l;
         }
-    l.mode = fused ? SL_MODE_FUSED_WINDOW : SL_MODE_HALF_WINDOW;
+    l.mode = coupled ? SL_MODE_SIMPLE : fused ? SL_MODE_FUSED_WINDOW : SL_MODE_HALF_WINDOW;
     l.tile_rows = 0;
     l.tile_words = 0;
     return l;
@@ -331,8 +332,12 @@ sl_status check_launch(const sl_lattice* h, sl_launch* l)
     }
     const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
                     0u, h->lay.nh};
-    if (h->params.model == SL_NE_COUPLED && l->mode != SL_MODE_SIMPLE && l->mode != SL_MODE_RESIDENT)
-        return fail(SL_E_UNSUPPORTED, "coupled NE lattices run SL_MODE_SIMPLE or SL_MODE_RESIDENT");
+    if (h->params.model == SL_NE_COUPLED) {
+        const bool row = l->mode == SL_MODE_HALF || l->mode == SL_MODE_FUSED;
+        if (!(l->mode == SL_MODE_SIMPLE || l->mode == SL_MODE_RESIDENT || (row && lut32_ok(h))))
+            return fail(SL_E_UNSUPPORTED, "coupled NE lattices run SL_MODE_SIMPLE, SL_MODE_RESIDENT, "
+                                          "or SL_MODE_HALF / SL_MODE_FUSED when every threshold is >= 1");
+    }
     switch (l->mode) {
         case SL_MODE_SIMPLE:
             return SL_OK;

@@ -1,7 +1,8 @@
 """GPU parity of the North-East model with the Ising coupling (Sec. 3.2, J != 0):
-the direct and the resident kernels must reproduce the oracle's lattice and
-every record bit for bit, the other schedules must be refused, and at J = 0,
-h = -1 and the T of c the model must equal the J = 0 NE model on the GPU too."""
+the direct, resident and whole-row kernels must reproduce the oracle's lattice
+and every record bit for bit, the window schedules (and the row schedules for
+a table with a zero threshold) must be refused, and at J = 0, h = -1 and the
+T of c the model must equal the J = 0 NE model on the GPU too."""
 import math
 
 import numpy as np
@@ -15,6 +16,9 @@ pytestmark = pytest.mark.gpu
 SIMPLE = (S.MODE_SIMPLE, 0, 0)
 RESIDENT = (S.MODE_RESIDENT, 0, 0)
 AUTO = (S.MODE_AUTO, 0, 0)
+# whole-row kernels: (mode, rows per strip, words per lane)
+ROW = [(S.MODE_FUSED, 0, 0), (S.MODE_HALF, 0, 0), (S.MODE_FUSED, 3, 1), (S.MODE_FUSED, 8, 2),
+       (S.MODE_HALF, 5, 4)]
 
 RATES = [dict(J=1.0, h=0.0, T=2.269, c=0.5), dict(J=1.0, h=0.3, T=2.0, c=0.6),
          dict(J=-0.7, h=0.2, T=1.5, c=0.4), dict(J=0.5, h=-1.1, T=math.inf, c=0.3)]
@@ -35,9 +39,9 @@ def _check(sp, nsweeps, launch=None, chunks=None):
     return g_r
 
 
-@pytest.mark.parametrize("L", [8, 16, 64, 136, 216, 512, 1040])
+@pytest.mark.parametrize("L", [8, 16, 64, 136, 216, 512, 1024, 1040, 2048])
 @pytest.mark.parametrize("rates", range(len(RATES)))
-@pytest.mark.parametrize("launch", [SIMPLE, RESIDENT, AUTO])
+@pytest.mark.parametrize("launch", [SIMPLE, RESIDENT, AUTO] + ROW)
 def test_coupled_shapes(L, rates, launch):
     n = 12 if L >= 512 else 30
     sp = S.Params(model=S.NE_COUPLED, L=L, seed=3 + L, record_capacity=64, **RATES[rates])
@@ -58,13 +62,30 @@ def test_coupled_resident_across_launch_chunks():
     _check(sp, 4100, launch=RESIDENT)
 
 
-@pytest.mark.parametrize("mode", [S.MODE_HALF, S.MODE_FUSED, S.MODE_HALF_WINDOW, S.MODE_FUSED_WINDOW])
-def test_streaming_schedules_refused(mode):
+@pytest.mark.parametrize("mode", [S.MODE_HALF_WINDOW, S.MODE_FUSED_WINDOW])
+def test_window_schedules_refused(mode):
     lat = S.Lattice(S.Params(model=S.NE_COUPLED, L=1024, J=1.0, T=2.5, c=0.5))
+    assert lat.get_launch()[0] == S.MODE_FUSED
     with pytest.raises(S.SpinlatError) as e:
         lat.set_launch(mode, 0, 0)
     assert e.value.status == 2
+    lat.close()
+
+
+def test_zero_thresholds_use_the_direct_kernel():
+    """T -> 0+: thresholds of energy-raising moves are 0, which the row
+    kernels' 32-bit "word <= thr - 1" cannot hold; AUTO takes the direct
+    kernel, the row schedules are refused, and the result is the oracle's."""
+    sp = S.Params(model=S.NE_COUPLED, L=1024, J=1.0, h=0.1, T=1e-300, c=0.6, seed=4,
+                  record_capacity=16)
+    lat = S.Lattice(sp)
     assert lat.get_launch()[0] == S.MODE_SIMPLE
+    for mode in (S.MODE_HALF, S.MODE_FUSED):
+        with pytest.raises(S.SpinlatError) as e:
+            lat.set_launch(mode, 0, 0)
+        assert e.value.status == 2
+    lat.close()
+    _check(sp, 6)
 
 
 def test_zero_coupling_equals_the_ne_model_on_the_gpu():
@@ -72,10 +93,11 @@ def test_zero_coupling_equals_the_ne_model_on_the_gpu():
     T = 2.0 / math.log((1.0 - c) / c)
     a = S.Params(model=S.NE_COUPLED, L=256, J=0.0, h=-1.0, T=T, c=c, seed=9, record_capacity=64)
     b = S.Params(model=S.NORTH_EAST, L=256, c=c, seed=9, record_capacity=64)
-    ga, ra = run_gpu(a, 40, launch=SIMPLE)
-    gb, rb = run_gpu(b, 40, launch=SIMPLE)
-    np.testing.assert_array_equal(ga, gb)
-    np.testing.assert_array_equal(ra, rb)
+    for launch in (SIMPLE, AUTO):
+        ga, ra = run_gpu(a, 40, launch=launch)
+        gb, rb = run_gpu(b, 40, launch=launch)
+        np.testing.assert_array_equal(ga, gb)
+        np.testing.assert_array_equal(ra, rb)
 
 
 def test_coupled_persistence_reset():
