@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(1024) k_row_half(SweepArgs a, RowGeom rg)
     __shared__ RowLuts lut;
     __shared__ uint32_t xch[2][16][2];
     uint64_t thr_up, thr_down;
-    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down, a.lut_n);
+    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down);
     __syncthreads();
 
     Obs o = {0, 0, 0, 0, 0};
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(1024) k_row_fused(SweepArgs a, RowGeom rg, con
     __shared__ RowLuts lut;
     __shared__ uint32_t xch[2][16][4];
     uint64_t thr_up, thr_down;
-    build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down, a.lut_n);
+    build_row_luts<KIND, 2>(lut, a.lut, thr_up, thr_down);
     __syncthreads();
 
     Obs o = {0, 0, 0, 0, 0};
@@ -135,6 +135,7 @@ hipError_t launch_row_half(const SweepArgs& a, int kind, int H, int D, hipStream
     if (a.g.dim == 2) {
         if (kind == KIND_ISING_HALF) launch_half_k<KIND_ISING_HALF, 2>(a, rg, s);
         else if (kind == KIND_ISING_ONE) launch_half_k<KIND_ISING_ONE, 2>(a, rg, s);
+        else if (a.lut_n > 2) launch_half_k<KIND_NE_COUPLED, 2>(a, rg, s);
         else launch_half_k<KIND_NE, 2>(a, rg, s);
     } else {
         if (kind == KIND_ISING_HALF) launch_half_k<KIND_ISING_HALF, 3>(a, rg, s);
@@ -150,6 +151,7 @@ hipError_t launch_row_fused(const SweepArgs& a, int kind, int H, int D, const ui
     if (!make_row_geom(a.g, H, D, true, rg)) return hipErrorInvalidValue;
     if (kind == KIND_ISING_HALF) launch_fused_k<KIND_ISING_HALF>(a, rg, src0, src1, dst0, dst1, s);
     else if (kind == KIND_ISING_ONE) launch_fused_k<KIND_ISING_ONE>(a, rg, src0, src1, dst0, dst1, s);
+    else if (a.lut_n > 2) launch_fused_k<KIND_NE_COUPLED>(a, rg, src0, src1, dst0, dst1, s);
     else launch_fused_k<KIND_NE>(a, rg, src0, src1, dst0, dst1, s);
     return hipGetLastError();
 }

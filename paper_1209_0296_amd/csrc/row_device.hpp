@@ -140,19 +140,17 @@ struct RowLuts {
     uint64_t e[3 * 2 * 13];  // spin-1 entries; spin-1/2 uses the first words as u32
 };
 
-// NE lattices with the Ising coupling (a table of more than the two J = 0
-// thresholds) get the spin-1/2 table, and thr_up = thr_down = kNeCoupled,
-// which no J = 0 threshold (<= 2^32) can equal.
-constexpr uint64_t kNeCoupled = ~0ull;
+// Kernel kind of NE lattices with the Ising coupling: the NE code paths (every
+// kind other than the two Ising ones), with the spin-1/2 table and move.
+constexpr int KIND_NE_COUPLED = 3;
 
 template <int KIND, int DIM>
 __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* table, uint64_t& thr_up,
-                                               uint64_t& thr_down, int table_n = 2)
+                                               uint64_t& thr_down)
 {
     constexpr int z = 2 * DIM;
-    const bool coupled = KIND == KIND_NE && table_n > 2;
     for (int t = threadIdx.x; t < 6 * (2 * z + 1); t += blockDim.x) {
-        if (KIND == KIND_ISING_HALF || coupled) {
+        if (KIND == KIND_ISING_HALF || KIND == KIND_NE_COUPLED) {
             if (t < 2 * (z + 1)) {
                 // entry nd + sneg*(z+1): nd neighbours at -1, sneg = (s == -1)
                 const int sneg = t / (z + 1), nd = t % (z + 1);
@@ -174,8 +172,8 @@ __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* tab
             lut.e[t] = thr | ((uint64_t)(uint32_t)(sp + 1) << 40);
         }
     }
-    thr_up = coupled ? kNeCoupled : table[0];
-    thr_down = coupled ? kNeCoupled : table[1];
+    thr_up = table[0];
+    thr_down = table[1];
 }
 
 struct Obs {
@@ -345,7 +343,7 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
             // north = row y-1; east = site x+1 (side word when p = 1)
             const uint32_t east = P ? side[d] : same.w[d];
             const uint32_t west = P ? same.w[d] : side[d];
-            if (thr_up == kNeCoupled)
+            if constexpr (KIND == KIND_NE_COUPLED)
                 out.w[d] = ne_coupled_word(own.w[d], up.w[d], east, up.w[d] + down.w[d] + east + west, g,
                                            colour, t, ks, lut);
             else
