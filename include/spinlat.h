@@ -334,8 +334,9 @@ sl_status sl_record_statistics(const sl_params* params, const sl_record* records
 sl_status sl_overlap(sl_lattice* lat, const int8_t* reference, int64_t* overlap);
 
 /* NE spin autocorrelation of Eq. 4 from an overlap: Phi = (overlap / N -
- * <s>^2) / (1 - <s>^2) with <s> = 2c - 1 (host-only, pure).  SL_E_INVALID for
- * Ising parameters. */
+ * <s>^2) / (1 - <s>^2) with <s> = 2c - 1 (host-only, pure); for SL_NE_COUPLED
+ * c is the initial density, which the caller sets to the equilibrium one when
+ * Phi should decay to 0.  SL_E_INVALID for Ising parameters. */
 sl_status sl_autocorrelation(const sl_params* params, int64_t overlap, double* phi);
 
 const char* sl_status_str(sl_status status);
