@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4  # 3.93e13 32-bit lane-ops/s in wave64 instructions
 # sources of the profiled kernels, hashed into profiles/traffic.json
 KERNEL_SOURCES = {
     "ising2d_L8192": ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
@@ -46,16 +47,34 @@ def sources_sha256(workload):
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE profile,
-    or None when the kernel sources changed since the counters were taken."""
+def _profile_entry(workload):
+    """The committed counter figures of a workload's kernel, or None when the
+    kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     entry = json.load(open(path)).get(workload)
-    if not entry:
+    if not entry or sources_sha256(workload) != entry["sources_sha256"]:
         return None
-    return entry["bytes_per_launch"] if sources_sha256(workload) == entry["sources_sha256"] else None
+    return entry
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE profile."""
+    entry = _profile_entry(workload)
+    return entry["bytes_per_launch"] if entry else None
+
+
+def valu_fraction(workload, per_launch_s):
+    """Issued VALU instructions per launch (SQ_INSTS_VALU of the committed
+    profile) over what the chip issues in the measured launch time: 256 CUs x
+    4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz."""
+    entry = _profile_entry(workload)
+    if not entry or "valu_insts_per_dispatch" not in entry:
+        return None
+    insts = entry["valu_insts_per_dispatch"]
+    return {"insts_per_launch": insts, "peak_insts_per_s": VALU_WAVE_INSTS_PER_S,
+            "frac": insts / (per_launch_s * VALU_WAVE_INSTS_PER_S)}
 
 
 def _lattice(S, cfg, T=None, record_capacity=4096):
@@ -260,7 +279,8 @@ def main():
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": {"per_launch_us": roof["per_launch_us"],
                             "algo_bytes_per_launch": roof["algo_bytes_per_launch"],
-                            "algo_bytes_per_attempt": ALGO_BYTES_PER_ATTEMPT},
+                            "algo_bytes_per_attempt": ALGO_BYTES_PER_ATTEMPT,
+                            "valu": valu_fraction("ising2d_L8192", roof["per_launch_us"] * 1e-6)},
         "cpu_baseline": cpu,
         "served": served_res,
         "secondary": secondary,
