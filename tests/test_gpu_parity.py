@@ -177,7 +177,7 @@ def test_split_runs_and_mixed_schedules():
     np.testing.assert_array_equal(g_s, o_s)
 
 
-@pytest.mark.parametrize("model,dim,two_s", [(0, 2, 1), (0, 3, 2), (1, 2, 1)])
+@pytest.mark.parametrize("model,dim,two_s", [(0, 2, 1), (0, 3, 2), (1, 2, 1), (4, 2, 1)])
 def test_checkpoint_restart(model, dim, two_s):
     """copy_spins at sweep a, recreate from that buffer with t0 = a, continue:
     identical to the uninterrupted run (the random numbers carry no state)."""
@@ -207,7 +207,8 @@ def test_buffer_init_roundtrip():
     import torch
     from workloads import random_lattice
 
-    for kw in (dict(L=64), dict(L=40, two_s=2), dict(dim=3, L=16), dict(model=1, L=64, c=0.3)):
+    for kw in (dict(L=64), dict(L=40, two_s=2), dict(dim=3, L=16), dict(model=1, L=64, c=0.3),
+               dict(model=4, L=64, J=1.0, h=0.2, T=2.0, c=0.5), dict(model=4, L=256, J=-0.5, T=1.5)):
         sp = S.Params(init=S.INIT_BUFFER, seed=3, record_capacity=8, **kw)
         start = random_lattice(sp.shape, two_s=sp.two_s, seed=5, model=sp.model,
                                flag_fraction=0.3)

@@ -64,7 +64,7 @@ def random_lattice(shape, two_s: int = 1, seed: int = 0, model: int = 0,
     """Seeded natural-order int8 lattice: Ising values in {-1,+1} or {-1,0,+1};
     NE bytes n | flag << 1 with n ~ Bernoulli(1/2) and flags set at random."""
     rng = np.random.default_rng(seed)
-    if model == 1:
+    if model != 0:  # every North-East model stores n | flag << 1
         n = rng.integers(0, 2, size=shape, dtype=np.int8)
         f = (rng.random(size=shape) < flag_fraction).astype(np.int8)
         return (n | (f << 1)).astype(np.int8)
