@@ -219,3 +219,18 @@ def test_equilibrium_4x4_matches_enumeration_of_its_component(J, h, T):
         mu, err = blocked_mean_err(series)
         assert abs(mu - ex) < 4 * err, (mu, ex, err)
     assert abs(OB.statistics(q, rec)["e"] - float(np.mean(e))) < 1e-12
+
+
+def test_thread_count_and_split_runs():
+    """The coupled half-sweep reads only the other colour, so the OpenMP thread
+    count and where a run is split cannot change the result."""
+    q = _coupled(L=32, J=1.0, h=0.1, T=2.2, c=0.6, seed=12)
+    a = O.init_lattice(q)
+    b, c = a.copy(), a.copy()
+    ra = O.run(q, a, 0, 20, nthreads=1)
+    rb = O.run(q, b, 0, 20, nthreads=4)
+    rc = np.vstack([O.run(q, c, 0, 7, nthreads=2), O.run(q, c, 7, 13, nthreads=3)])
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(ra, rb)
+    np.testing.assert_array_equal(ra, rc)
