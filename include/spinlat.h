@@ -243,10 +243,11 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
  * lists at the start of it and places every job's lattice and record ring in
  * the rest.  A job is admitted only if its footprint (sl_batch_job_bytes) fits
  * in the free arena space; removing a job returns its space.
- * Batched jobs need L % 8 == 0 and a checkerboard model (SL_ISING or
- * SL_NORTH_EAST).  Jobs whose colour row splits into row groups
- * of at most 64 lanes run the whole-row kernels, the others the column-window
- * kernels (also spin-1/2 jobs with a zero threshold).
+ * Batched jobs need L % 8 == 0 and a checkerboard model (SL_ISING,
+ * SL_NORTH_EAST or SL_NE_COUPLED).  Jobs whose colour row splits into row
+ * groups of at most 64 lanes run the whole-row kernels, the others the
+ * column-window kernels (also spin-1/2 jobs with a zero threshold); coupled NE
+ * jobs must fit the whole-row kernels (SL_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------- */
 typedef struct sl_batch sl_batch;
 

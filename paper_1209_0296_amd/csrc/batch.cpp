@@ -90,6 +90,12 @@ struct JobHost {
     size_t table_n = 0;
 };
 
+// Kernel kind of a job's class: the model kind, with coupled NE jobs apart.
+int class_kind(const JobHost& J)
+{
+    return J.params.model == SL_NE_COUPLED ? kBatchKindNeCoupled : J.kind;
+}
+
 }  // namespace
 
 struct sl_batch {
@@ -196,16 +202,19 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     if (is_sub_lattice(p->model))
         return fail(SL_E_UNSUPPORTED, "batched jobs use the checkerboard sweep; the NE "
                                       "sub-lattice algorithm runs as a single lattice");
-    if (p->model == SL_NE_COUPLED)
-        return fail(SL_E_UNSUPPORTED, "coupled NE lattices run as single lattices");
     *foot = job_foot(p, cfg->record_capacity);
     *table_n = build_table(p, table);
     bool lut32 = true;
     for (size_t i = 0; i < *table_n; ++i)
         if (table[i] == 0) lut32 = false;
     const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim);
-    if (!batch_geom(geom_of(p, foot->nh), H, lut32 || kind_of(p) != KIND_ISING_HALF, *geom))
+    const bool coupled = p->model == SL_NE_COUPLED;
+    const bool spin_half_table = kind_of(p) == KIND_ISING_HALF || coupled;
+    if (!batch_geom(geom_of(p, foot->nh), H, lut32 || !spin_half_table, *geom))
         return fail(SL_E_UNSUPPORTED, "L = %d does not fit the batched kernels", p->L);
+    if (coupled && geom->D == 0)
+        return fail(SL_E_UNSUPPORTED, "batched coupled NE jobs need a colour row that fits one wave "
+                                      "and every threshold >= 1 (L = %d)", p->L);
     return SL_OK;
 }
 
@@ -324,7 +333,7 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
     hj->acc = ring_of(b, j);
     hj->key0 = (uint32_t)J.params.seed;
     hj->key1 = (uint32_t)(J.params.seed >> 32);
-    hj->cls = batch_class(J.kind, J.params.dim, J.geom.D);
+    hj->cls = batch_class(class_kind(J), J.params.dim, J.geom.D);
     std::memcpy(hj->rg_words, J.geom.bytes, sizeof(hj->rg_words));
     std::memcpy(hj->table, J.table, J.table_n * sizeof(uint64_t));
     hipError_t e = hipMemcpyAsync(d_jobs(b) + j, hj, sizeof(BatchJob), hipMemcpyHostToDevice, b->stream);
@@ -379,12 +388,13 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     // the work list grouped by kernel variant (kind, dim, words per lane), so
     // neighbouring workgroups of the one launch run the same code
     uint64_t nwg = 0;
-    for (int kind : {KIND_ISING_HALF, KIND_ISING_ONE, KIND_NE})
+    for (int kind : {(int)KIND_ISING_HALF, (int)KIND_ISING_ONE, (int)KIND_NE, kBatchKindNeCoupled})
         for (int dim : {2, 3})
             for (int D : {4, 2, 1, 0}) {
                 for (uint32_t j = 0; j < top; ++j) {
                     const JobHost& J = b->jobs[j];
-                    if (!J.used || !budget[j] || J.kind != kind || J.params.dim != dim || J.geom.D != D)
+                    if (!J.used || !budget[j] || class_kind(J) != kind || J.params.dim != dim ||
+                        J.geom.D != D)
                         continue;
                     const uint32_t per = J.geom.items_per_wg;
                     const uint32_t k = (J.geom.nitems + per - 1) / per;

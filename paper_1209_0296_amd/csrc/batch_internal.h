@@ -46,6 +46,10 @@ struct RowGeomHost {
 // 64-lane column windows (D = 0).
 bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out);
 
+// Class kind of coupled NE jobs (SL_NE_COUPLED): the whole-row kernels'
+// coupled instantiation; such jobs need a row class (D != 0).
+constexpr int kBatchKindNeCoupled = 3;
+
 // Variant index of a job for the one-launch kernel: kind, dimension and D.
 inline uint32_t batch_class(int kind, int dim, int D)
 {

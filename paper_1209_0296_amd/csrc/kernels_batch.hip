@@ -104,6 +104,19 @@ __device__ __forceinline__ void dispatch_d(uint32_t d, const BatchJob* jobs, con
     else batch_window_body<KIND, DIM>(jobs, dyn, w, colour, step, lds.win);
 }
 
+// Coupled NE jobs run only the whole-row bodies (the host admits no other).
+template <int KIND, int DIM>
+__device__ __forceinline__ void dispatch_rows(uint32_t d, const BatchJob* jobs, const uint32_t* dyn,
+                                              const BatchWG w, uint32_t colour, uint32_t step, BatchLds& lds,
+                                              uint32_t (&xch)[2][16][2])
+{
+    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, step, lds.row, xch);
+    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, step, lds.row, xch);
+    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, step, lds.row, xch);
+}
+
+static_assert(kBatchKindNeCoupled == KIND_NE_COUPLED, "batch class kind of coupled NE jobs");
+
 __global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ jobs,
                                                    const uint32_t* __restrict__ dyn,
                                                    const BatchWG* __restrict__ wgs, uint32_t colour,
@@ -120,8 +133,10 @@ __global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ 
     } else if (kind == KIND_ISING_ONE) {
         if (dim3d) dispatch_d<KIND_ISING_ONE, 3>(d, jobs, dyn, w, colour, step, lds, xch);
         else dispatch_d<KIND_ISING_ONE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
-    } else {
+    } else if (kind == KIND_NE) {
         dispatch_d<KIND_NE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
+    } else {
+        dispatch_rows<KIND_NE_COUPLED, 2>(d, jobs, dyn, w, colour, step, lds, xch);
     }
 }
 

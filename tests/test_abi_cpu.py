@@ -153,9 +153,13 @@ def test_balanced_shapes_accepted(B, lam):
 def test_sub_lattice_jobs_not_batched():
     cfg = S.batch_config(max_jobs=4, record_capacity=8)
     n = ctypes.c_size_t()
-    for model in (S.NE_SUBLATTICE, S.NE_COUPLED):
-        cp = S.Params(model=model, L=64).c_struct()
-        assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
+    cp = S.Params(model=S.NE_SUBLATTICE, L=64).c_struct()
+    assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
+    # coupled NE jobs: whole-row classes only (rows within one wave, thresholds >= 1)
+    for kw, code in ((dict(L=64), 0), (dict(L=512), 0), (dict(L=2056), 2), (dict(L=936), 2),
+                     (dict(L=64, T=1e-300), 2)):
+        cp = S.Params(model=S.NE_COUPLED, J=1.0, h=0.1, **{"T": 2.0, **kw}).c_struct()
+        assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == code, kw
 
 
 def _records_from(rec):

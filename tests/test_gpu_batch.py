@@ -52,6 +52,32 @@ def test_mixed_batch_matches_each_job_alone():
     b.close()
 
 
+def test_coupled_ne_jobs_in_a_mixed_batch():
+    """Coupled NE jobs (rows within one wave) share launches with Ising and
+    J = 0 NE jobs and still equal the oracle run of each job alone."""
+    jobs = [
+        S.Params(model=S.NE_COUPLED, L=64, J=1.0, h=0.2, T=2.0, c=0.6, seed=31),
+        S.Params(model=S.NE_COUPLED, L=40, J=-0.5, h=0.0, T=1.5, c=0.4, seed=32),   # D = 1 rows
+        S.Params(model=S.NE_COUPLED, L=512, J=1.0, h=-0.1, T=2.5, c=0.5, seed=33),  # D = 4 rows
+        S.Params(model=S.NORTH_EAST, L=64, c=0.2, seed=34),
+        S.Params(L=64, T=2.269, seed=35),
+        S.Params(L=936, T=2.3, seed=36),                                            # window kernel
+    ]
+    b = S.Batch(arena_bytes=32 << 20, max_jobs=8, record_capacity=32)
+    ids = [b.add(p, sweeps=20) for p in jobs]
+    recs = {i: [S.records_to_array(b.measure(i))] for i in ids}
+    b.sweep(9)
+    for i in ids:
+        recs[i].append(S.records_to_array(b.measure(i)))
+    b.sweep(50)
+    for i, p in zip(ids, jobs):
+        print(f"case batch coupled job {i} model={p.model} L={p.L}", flush=True)
+        assert b.status(i)[:2] == (20, 0)
+        recs[i].append(S.records_to_array(b.measure(i)))
+        _check_job(b, i, p, recs[i], 20)
+    b.close()
+
+
 def test_uneven_budgets_and_late_admission():
     b = S.Batch(arena_bytes=32 << 20, max_jobs=8, record_capacity=16)
     early = S.Params(L=128, T=2.3, seed=21)
