@@ -38,12 +38,12 @@ RECORD_WORDS = 5  # t, bond_sum, mag, accepted, unflipped
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    """Compile the oracle with gcc (-O3, no fast-math, no contraction, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
         os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "spinlat_oracle.h"))
     ):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+        cmd = ["gcc", "-O3", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
                "-shared", "-std=c11", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)

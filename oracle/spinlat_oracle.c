@@ -142,7 +142,8 @@ static inline int64_t idx3(int L, int x, int y, int z)
     return ((int64_t)z * L + y) * L + x;
 }
 
-static inline int wrap(int a, int L) { return (a % L + L) % L; }
+/* periodic index for a in [-L, 2L): every caller steps at most one site past an edge */
+static inline int wrap(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
 
 static int nsites_dims(const or_params* p, int64_t* N)
 {
@@ -280,11 +281,14 @@ static int64_t half_sweep_ne(const or_params* p, int8_t* s, uint32_t t, uint32_t
             if ((uint32_t)((x + y) & 1) != colour) continue;
             int64_t i = idx3(L, x, y, 0);
             uint64_t k = (uint64_t)i >> 1;
-            uint32_t u = or_rand(p->seed, OR_TAG_SWEEP, t, colour, k, 1, 0);
             int n = s[i] & 1;
             int north = s[idx3(L, x, wrap(y - 1, L), 0)] & 1;
             int east = s[idx3(L, wrap(x + 1, L), y, 0)] & 1;
             if (!(north && east)) continue;          /* kinetic constraint */
+            /* the site's word R(seed, SWEEP, t, colour, k, 1, 0) is a pure
+             * function of its indices, so it is only evaluated for a move the
+             * constraint allows */
+            uint32_t u = or_rand(p->seed, OR_TAG_SWEEP, t, colour, k, 1, 0);
             uint64_t thr;
             if (coupled) {
                 int south = s[idx3(L, x, wrap(y + 1, L), 0)] & 1;
@@ -321,6 +325,8 @@ void or_recount(const or_params* p, const int8_t* s, int64_t out[3])
     const int L = p->L;
     const int nz = (p->dim == 3) ? L : 1;
     int64_t bond = 0, mag = 0, unflipped = 0;
+    /* integer sums: sharing rows out among threads cannot change them */
+#pragma omp parallel for schedule(static) collapse(2) reduction(+ : bond, mag, unflipped)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
