@@ -32,8 +32,8 @@ VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4  # 3.93e13 32-bit lane-ops/s in wave
 # sources of the profiled kernels, hashed into profiles/traffic.json
 KERNEL_SOURCES = {
     "ising2d_L8192": ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
-                      "spinlat_internal.h"),
-    "ne2d_sub_L4096": ("kernels_ne_sub.hip", "philox.hpp", "spinlat_internal.h"),
+                      "spinlat_internal.h", "host_logic.h"),
+    "ne2d_sub_L4096": ("ne_sub_device.hpp", "philox.hpp", "spinlat_internal.h", "host_logic.h"),
 }
 
 
@@ -128,6 +128,39 @@ def time_workload(S, torch, name, cfg, steps, warmup, T=None):
     }
 
 
+def host_description():
+    """What the CPU baseline ran on: core counts, CPU model, oracle build flags."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "oracle_build": "gcc -O3 -fno-fast-math -ffp-contract=off -fopenmp (oracle/__init__.py)"}
+
+
+def baseline_threads():
+    """All the host cores this process may use: the OpenMP thread count the
+    environment sets for this machine's share, else every CPU in the affinity
+    mask."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(cfg, sweeps, threads, single_sweeps=2):
     """The oracle as it is, on the host cores, on `sweeps` sweeps of the same
     lattice; and on one thread over `single_sweeps` sweeps."""
@@ -149,6 +182,7 @@ def cpu_baseline(cfg, sweeps, threads, single_sweeps=2):
         d1 = time.perf_counter() - t0
         out["single_thread_value"] = p.nsites * single_sweeps / d1
         out["single_thread_sample"] = f"{single_sweeps} further sweeps on 1 thread, {d1:.1f} s"
+    out["host"] = host_description()
     return out
 
 
@@ -258,7 +292,7 @@ def main():
               f"p99 {served_res['p99_latency_s']:.3g} s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
+        threads = baseline_threads()
         cpu = cpu_baseline(cfg2, args.cpu_sweeps, threads)
         print(f"# oracle: {cpu['value']:.4g} attempts/s on {threads} threads", file=sys.stderr,
               flush=True)

@@ -110,7 +110,8 @@ typedef enum sl_model {
     SL_NE_SUBLATTICE_BALANCED = 3, /* its balanced variant: colour 0 then colour 1 sites
                                       per iteration, four launches per sweep */
     SL_NE_COUPLED = 4 /* NE constraint with the Ising rates of (J, h, T), checkerboard
-                         half-sweeps; SL_MODE_SIMPLE and SL_MODE_RESIDENT only */
+                         half-sweeps; SL_MODE_SIMPLE, SL_MODE_RESIDENT, and SL_MODE_HALF /
+                         SL_MODE_FUSED when every threshold is >= 1 */
 } sl_model;
 
 typedef enum sl_init {
@@ -173,20 +174,34 @@ typedef struct sl_launch {
     int32_t reserved;
 } sl_launch;
 
-/* Bytes of device memory the lattice needs (spins, record ring, tables).
- * Host-only, pure.  SL_E_INVALID / SL_E_UNSUPPORTED as sl_create_lattice. */
+/* Bytes of device memory the lattice needs (Alg. I steps 1-2: the lattice
+ * lives in GPU memory; here two copies of both colour arrays, the per-sweep
+ * record ring and the threshold table).  Host-only, pure; the caller then
+ * allocates that many bytes, 256-byte aligned.  SL_E_INVALID /
+ * SL_E_UNSUPPORTED / SL_E_OVERFLOW as sl_create_lattice. */
 sl_status sl_query_bytes(const sl_params* params, size_t* device_bytes);
 
-/* Threshold table the kernels use (host-only, pure).  Ising and
- * SL_NE_COUPLED: 4*(4*dim+1) entries, [di][nsum + 2*dim] for
- * s'-s = {-2,-1,+1,+2}[di]; the J = 0 NE models: {up, down}.
- * Each entry is in [0, 2^32]. */
+/* Threshold table the kernels use (Sec. 3.1: P_acc = min[1, exp(-dH/T)] with
+ * the energy of Eq. 2 and a field; Sec. 3.2: the NE rates at up-density c),
+ * as floor(P_acc 2^32) in double precision.  Host-only, pure: it takes the
+ * parameters, not a lattice, so it can be read before any device work.
+ * Ising and SL_NE_COUPLED: 4*(4*dim+1) entries, [di][nsum + 2*dim] for
+ * s'-s = {-2,-1,+1,+2}[di]; the J = 0 NE models: {up, down}.  Each entry is in
+ * [0, 2^32].  out (host, cap entries) receives them, *n_out the count;
+ * SL_E_BUFFER (and *n_out set) if cap is too small. */
 sl_status sl_threshold_table(const sl_params* params, uint64_t* out, size_t cap,
                              size_t* n_out);
 
 /* Bind the caller's device buffer and stream, initialise the lattice and
- * record r_0.  Work is enqueued on the stream; the call does not synchronise.
- * hip_stream is a hipStream_t (NULL: the default stream). */
+ * record r_0 (Alg. I step 1: random initialisation -- done here on the GPU
+ * from the counter-based words of tag 1 rather than on the CPU; Sec. 3.2: NE
+ * sites up with probability c; or a copy of init_spins).  device_buf
+ * (device, >= sl_query_bytes bytes, 256-byte aligned) is borrowed, never
+ * freed; hip_stream is a hipStream_t (NULL: the default stream).  Work is
+ * enqueued on the stream; the call synchronises once, after the table upload.
+ * Errors: SL_E_INVALID (parameters), SL_E_UNSUPPORTED (no kernel for the
+ * shape), SL_E_OVERFLOW (t0), SL_E_BUFFER (buffer NULL, small or misaligned),
+ * SL_E_HIP. */
 sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t bytes,
                             void* hip_stream, sl_lattice** out);
 
@@ -195,31 +210,52 @@ sl_status sl_create_lattice(const sl_params* params, void* device_buf, size_t by
  * into row groups of <= 64 lanes or a multiple of 64 lanes up to 1024, and for
  * spin-1/2 every threshold >= 1; the window modes take any shape).  NE
  * sub-lattice lattices have one schedule and accept only SL_MODE_AUTO;
- * SL_NE_COUPLED lattices take SL_MODE_SIMPLE and SL_MODE_RESIDENT. */
+ * SL_NE_COUPLED lattices take SL_MODE_SIMPLE, SL_MODE_RESIDENT, and the
+ * whole-row modes when every threshold is >= 1.  The schedule changes speed
+ * only, never a result (the random numbers are keyed by sweep and site; the
+ * paper's kernel boundary between colours, Alg. I steps 6-7, is one choice of
+ * barrier among several here). */
 sl_status sl_set_launch(sl_lattice* lat, const sl_launch* launch);
 sl_status sl_get_launch(const sl_lattice* lat, sl_launch* launch);
 
-/* Enqueue n sweeps (Monte Carlo steps) on the stream; asynchronous.  Fails
- * with SL_E_STATE (nothing enqueued) if the unread records would exceed
- * record_capacity, SL_E_OVERFLOW if the sweep index would reach 2^32. */
+/* Enqueue n sweeps on the stream; asynchronous (Alg. I steps 5-7: colour 0,
+ * then colour 1, a kernel end or a workgroup barrier between them; one sweep is
+ * one Monte Carlo step, an attempt per site, as defined after Alg. I).  Each
+ * sweep adds one record to the ring.  Fails with SL_E_STATE (nothing
+ * enqueued) if the unread records would exceed record_capacity, SL_E_OVERFLOW
+ * if a sweep index would reach 2^32 (NE sub-lattices 2^31, balanced 2^30);
+ * both checks hold for any n, including 2^64 - 1. */
 sl_status sl_sweep(sl_lattice* lat, uint64_t n);
 
 /* Synchronise the stream and move all unread records to out[0..n) (host
- * memory).  SL_E_BUFFER (nothing drained) if cap is smaller than the count. */
+ * memory, cap records).  Sec. 3.1 averages observables from lattice copies
+ * the GPU sends to the host from time to time; here the sweep reduces bond
+ * sum, magnetisation, accepted moves and persistence on the device every sweep
+ * and this call copies only those records.  SL_E_BUFFER (nothing drained) if
+ * cap is smaller than the count. */
 sl_status sl_measure(sl_lattice* lat, sl_record* out, size_t cap, size_t* n_out);
 
-/* Number of unread records and the index of the next sweep. */
+/* Number of unread records and the index of the next sweep (host state, no
+ * device work; either pointer may be NULL). */
 sl_status sl_status_counts(const sl_lattice* lat, uint64_t* pending, uint64_t* next_t);
 
-/* Enqueue a copy of the lattice into device_out (L^dim bytes, natural
- * row-major order, NE bytes include the flag bit).  Asynchronous. */
+/* Enqueue a copy of the lattice into device_out (device, n >= L^dim bytes,
+ * natural row-major order [z][y][x], NE bytes n | flag << 1).  Asynchronous;
+ * the caller copies to the host if it wants one (Alg. I step 8 and Sec. 3.1:
+ * the lattice is copied out from time to time; also the checkpoint that
+ * SL_INIT_BUFFER with t0 resumes from).  SL_E_BUFFER if device_out is NULL or
+ * n too small. */
 sl_status sl_copy_spins(sl_lattice* lat, int8_t* device_out, size_t n);
 
-/* NE (either algorithm): clear every "has flipped" flag; the persistence
- * origin becomes the current sweep.  Asynchronous.  SL_E_STATE for Ising. */
+/* NE (every NE model): clear every "has flipped" flag; the persistence
+ * origin becomes the current sweep (the time origin of Phi(t), Eq. 4, and of
+ * the persistence function the NE workloads record; the paper does not define
+ * persistence, the flag is this library's reading).  Asynchronous.
+ * SL_E_STATE for Ising. */
 sl_status sl_reset_persistence(sl_lattice* lat);
 
-/* Release the handle (never frees the borrowed buffer).  Synchronises. */
+/* Release the handle (never frees the borrowed buffer or the stream).
+ * Synchronises the stream first; unread records are lost. */
 sl_status sl_destroy(sl_lattice* lat);
 
 /* Observables of n records (host-only, pure, double precision): Ising

@@ -11,7 +11,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspinlat.so")
 SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "kernels_row.hip", "kernels_batch.hip",
-           "kernels_ne_sub.hip", "runtime.cpp", "batch.cpp"]
+           "kernels_ne_sub.hip", "kernels_ne_sub_b8.hip", "kernels_ne_sub_b16.hip",
+           "kernels_ne_sub_b32.hip", "kernels_ne_sub_b64.hip", "host_logic.cpp", "runtime.cpp",
+           "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -25,18 +27,31 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
+def _headers_mtime() -> float:
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".hpp"))]
+    paths.append(os.path.join(ROOT, "include", "spinlat.h"))
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every source and link the shared library.  By default every
+    object is rebuilt; with incremental=True only objects older than their
+    source or any header are."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    hdr = _headers_mtime() if incremental else 0.0
     cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        objs.append(obj)
+        path = os.path.join(CSRC, src)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(
+                hdr, os.path.getmtime(path)):
+            continue
+        cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         cmds.append(cmd)
-        objs.append(obj)
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for cmd in cmds:
@@ -55,4 +70,4 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-q" not in sys.argv)
+    build(verbose="-q" not in sys.argv, incremental="--incremental" in sys.argv)

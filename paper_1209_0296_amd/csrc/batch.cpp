@@ -9,7 +9,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <map>
 #include <new>
 #include <vector>
 
@@ -105,7 +104,7 @@ struct sl_batch {
     hipStream_t stream;
     BaseLayout base;
     std::vector<JobHost> jobs;
-    std::map<size_t, size_t> free_blocks;  // heap offset -> size
+    FreeList heap;  // free ranges of the job heap
     BatchJob* h_job;     // pinned staging of one job-table entry
     uint32_t* h_dyn;     // pinned [max_jobs][kDynWords]
     BatchWG* h_wgs;      // pinned [max_wg]
@@ -118,38 +117,6 @@ namespace {
 BatchJob* d_jobs(const sl_batch* b) { return reinterpret_cast<BatchJob*>(b->arena + b->base.jobs); }
 uint32_t* d_dyn(const sl_batch* b) { return reinterpret_cast<uint32_t*>(b->arena + b->base.dyn); }
 BatchWG* d_wgs(const sl_batch* b) { return reinterpret_cast<BatchWG*>(b->arena + b->base.wgs); }
-
-bool heap_alloc(sl_batch* b, size_t bytes, size_t* off)
-{
-    for (auto it = b->free_blocks.begin(); it != b->free_blocks.end(); ++it) {
-        if (it->second >= bytes) {
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t roff = it->first + bytes;
-            b->free_blocks.erase(it);
-            if (rest) b->free_blocks[roff] = rest;
-            return true;
-        }
-    }
-    return false;
-}
-
-void heap_free(sl_batch* b, size_t off, size_t bytes)
-{
-    auto it = b->free_blocks.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != b->free_blocks.end() && it->first + it->second == next->first) {
-        it->second += next->second;
-        b->free_blocks.erase(next);
-    }
-    if (it != b->free_blocks.begin()) {
-        auto prev = std::prev(it);
-        if (prev->first + prev->second == it->first) {
-            prev->second += it->second;
-            b->free_blocks.erase(it);
-        }
-    }
-}
 
 Geom geom_of(const sl_params* p, uint64_t nh)
 {
@@ -269,7 +236,7 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
     b->base = base;
     b->jobs.resize(cfg->max_jobs);
     const size_t heap = round_up(base.heap, kAlign);
-    if (arena_bytes > heap) b->free_blocks[heap] = (arena_bytes - heap) / kAlign * kAlign;
+    b->heap.reset(heap, arena_bytes > heap ? (arena_bytes - heap) / kAlign * kAlign : 0);
     b->h_job = nullptr;
     b->h_dyn = nullptr;
     b->h_wgs = nullptr;
@@ -311,12 +278,12 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
     JobHost J;
     sl_status st = prepare_job(&b->cfg, params, &J.params, &J.foot, &J.geom, J.table, &J.table_n);
     if (st != SL_OK) return st;
-    if (J.params.t0 + sweeps > (1ull << 32))
-        return fail(SL_E_OVERFLOW, "t0 + sweeps would reach 2^32");
+    if (sweeps > (1ull << 32) - J.params.t0)  // validate() keeps t0 < 2^32
+        return fail(SL_E_OVERFLOW, "t0 + sweeps would pass 2^32");
     uint32_t j = 0;
     while (j < b->jobs.size() && b->jobs[j].used) ++j;
     if (j == b->jobs.size()) return fail(SL_E_STATE, "job table full (%u jobs)", b->cfg.max_jobs);
-    if (!heap_alloc(b, J.foot.total, &J.off))
+    if (!b->heap.alloc(J.foot.total, &J.off))
         return fail(SL_E_BUFFER, "arena has no free block of %zu bytes for this job", J.foot.total);
     J.used = true;
     J.kind = kind_of(&J.params);
@@ -358,7 +325,7 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // h_job is reused by the next add
     if (e != hipSuccess) {
-        heap_free(b, J.off, J.foot.total);
+        b->heap.release(J.off, J.foot.total);
         b->jobs[j] = JobHost();
         return hip_fail(e, "batch add");
     }
@@ -530,7 +497,7 @@ sl_status sl_batch_remove(sl_batch* b, uint32_t job_id)
     hipError_t e = hipStreamSynchronize(b->stream);  // no queued launch may still use its memory
     if (e != hipSuccess) return hip_fail(e, "batch remove");
     JobHost& J = b->jobs[job_id];
-    heap_free(b, J.off, J.foot.total);
+    b->heap.release(J.off, J.foot.total);
     J = JobHost();
     return SL_OK;
 }

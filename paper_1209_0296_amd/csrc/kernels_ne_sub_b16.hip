@@ -1,0 +1,12 @@
+// kernels_ne_sub_b16.hip -- NE sub-lattice kernels for sub-lattices of side 16
+// (device code in ne_sub_device.hpp).
+#include "ne_sub_device.hpp"
+
+namespace spinlat {
+
+hipError_t launch_ne_sub_b16(const NeSubArgs& a, int lambda, bool balanced, hipStream_t s)
+{
+    return nesub::launch_side<16>(a, lambda, balanced, s);
+}
+
+}  // namespace spinlat

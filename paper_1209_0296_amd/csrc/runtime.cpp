@@ -19,6 +19,7 @@
 
 #include "../../include/spinlat.h"
 #include "host_common.h"
+#include "runtime_internal.h"
 #include "spinlat_internal.h"
 
 using namespace spinlat;
@@ -26,145 +27,9 @@ using namespace spinlat;
 namespace spinlat {
 namespace host {
 
-thread_local char g_err[512] = "";
-
-const char* last_error() { return g_err; }
-
-sl_status fail(sl_status st, const char* fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    std::vsnprintf(g_err, sizeof g_err, fmt, ap);
-    va_end(ap);
-    return st;
-}
-
 sl_status hip_fail(hipError_t e, const char* what)
 {
     return fail(SL_E_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-bool is_sub_lattice(int model) { return model == SL_NE_SUBLATTICE || model == SL_NE_SUBLATTICE_BALANCED; }
-
-// Sweep indices stay below this: the launch index (2 or 4 per sweep) is 32-bit.
-uint64_t sweep_limit(int model)
-{
-    if (model == SL_NE_SUBLATTICE) return 1ull << 31;
-    if (model == SL_NE_SUBLATTICE_BALANCED) return 1ull << 30;
-    return 1ull << 32;
-}
-
-int kind_of(const sl_params* p)
-{
-    if (p->model != SL_ISING) return KIND_NE;
-    return p->two_s == 1 ? KIND_ISING_HALF : KIND_ISING_ONE;
-}
-
-sl_status validate(const sl_params* p)
-{
-    if (!p) return fail(SL_E_INVALID, "params is NULL");
-    if (p->abi_version != SL_ABI_VERSION)
-        return fail(SL_E_INVALID, "abi_version %u != %u", p->abi_version, SL_ABI_VERSION);
-    if (p->model != SL_ISING && p->model != SL_NORTH_EAST && p->model != SL_NE_SUBLATTICE &&
-        p->model != SL_NE_SUBLATTICE_BALANCED && p->model != SL_NE_COUPLED)
-        return fail(SL_E_INVALID, "unknown model %d", p->model);
-    if (p->dim != 2 && p->dim != 3) return fail(SL_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
-    if (p->L < 2 || (p->L & 1))
-        return fail(SL_E_INVALID, "L must be even and >= 2 (got %d): the checkerboard needs a "
-                                  "bipartite periodic lattice", p->L);
-    if (p->two_s != 1 && p->two_s != 2)
-        return fail(SL_E_INVALID, "two_s must be 1 (spin-1/2) or 2 (spin-1), got %d", p->two_s);
-    if (p->init != SL_INIT_COLD && p->init != SL_INIT_RANDOM && p->init != SL_INIT_BUFFER)
-        return fail(SL_E_INVALID, "unknown init %d", p->init);
-    if (p->init == SL_INIT_BUFFER && !p->init_spins)
-        return fail(SL_E_INVALID, "SL_INIT_BUFFER needs init_spins");
-    if (p->model == SL_ISING || p->model == SL_NE_COUPLED) {
-        if (!(p->T > 0.0)) return fail(SL_E_INVALID, "T must be > 0 (got %g)", p->T);
-        if (std::isnan(p->J) || std::isnan(p->h) || std::isinf(p->J) || std::isinf(p->h))
-            return fail(SL_E_INVALID, "J and h must be finite");
-    }
-    if (p->model != SL_ISING) {
-        if (p->dim != 2) return fail(SL_E_INVALID, "the North-East model is two-dimensional");
-        if (p->two_s != 1) return fail(SL_E_INVALID, "the North-East model has binary sites");
-        if (!(p->c > 0.0 && p->c < 1.0))
-            return fail(SL_E_INVALID, "c must lie in (0, 1) (got %g)", p->c);
-        if (p->init == SL_INIT_COLD)
-            return fail(SL_E_INVALID, "NE lattices start from Bernoulli(c) or a buffer");
-    }
-    if (is_sub_lattice(p->model)) {
-        const bool bal = p->model == SL_NE_SUBLATTICE_BALANCED;
-        const int B = p->ne_side, lam = p->ne_lambda, per = bal ? 8 : 2;
-        if (B < 2 || (B & 1) || lam < 1 || p->L % B != 0 || (B * B) % (per * lam) != 0)
-            return fail(SL_E_INVALID, "sub-lattices need an even B with L %% B == 0 and "
-                                      "B^2 %% (%d lambda) == 0 (L %d, B %d, lambda %d)",
-                        per, p->L, B, lam);
-        if (!ne_sub_supported((uint32_t)p->L, B, lam, bal))
-            return fail(SL_E_UNSUPPORTED, "the sub-lattice kernels take B in {8,16,32,64} and "
-                                          "lambda a power of two in [2,128] (B %d, lambda %d)",
-                        B, lam);
-        if (p->t0 >= sweep_limit(p->model))
-            return fail(SL_E_OVERFLOW, "t0 must be < %llu (launch indices are 32-bit)",
-                        (unsigned long long)sweep_limit(p->model));
-    }
-    if (p->t0 >= (1ull << 32)) return fail(SL_E_OVERFLOW, "t0 must be < 2^32");
-    if (p->record_capacity < 1 || p->record_capacity > (1ull << 32))
-        return fail(SL_E_INVALID, "record_capacity must be in [1, 2^32]");
-    if (p->L % 8 != 0)
-        return fail(SL_E_UNSUPPORTED, "kernels need L %% 8 == 0 (got %d)", p->L);
-    // the first counter word holds the Philox group index (k / G) in 32 bits
-    const uint64_t nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
-    const uint64_t groups = (nsites / 2) / (p->two_s == 1 ? 4 : 2);
-    if (groups > (1ull << 32))
-        return fail(SL_E_UNSUPPORTED, "lattice too large for the 32-bit Philox group index");
-    return SL_OK;
-}
-
-Layout layout_of(const sl_params* p)
-{
-    Layout l{};
-    l.nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
-    l.nh = l.nsites / 2;
-    l.col_bytes = round_up(l.nh, kAlign);
-    for (int b = 0; b < 2; ++b)
-        for (int c = 0; c < 2; ++c) l.off_col[b][c] = (size_t)(2 * b + c) * l.col_bytes;
-    l.off_acc = 4 * l.col_bytes;
-    l.off_out = l.off_acc + round_up(p->record_capacity * kSlotWords * sizeof(int64_t), kAlign);
-    l.off_lut = l.off_out + round_up(p->record_capacity * kRecordWords * sizeof(int64_t), kAlign);
-    l.total = l.off_lut + round_up(kMaxLut * sizeof(uint64_t), kAlign);
-    return l;
-}
-
-// ---- Metropolis thresholds (double precision, host) ------------------------
-
-uint64_t thr_from_prob(double pr)
-{
-    if (!(pr < 1.0)) return 1ull << 32;
-    if (!(pr > 0.0)) return 0;
-    return (uint64_t)std::floor(pr * 4294967296.0);
-}
-
-uint64_t thr_from_energy(double dE, double T)
-{
-    if (dE <= 0.0) return 1ull << 32;
-    return thr_from_prob(std::exp(-dE / T));
-}
-
-size_t build_table(const sl_params* p, uint64_t* out)
-{
-    if (p->model != SL_ISING && p->model != SL_NE_COUPLED) {
-        out[0] = thr_from_prob(p->c / (1.0 - p->c));  // up-flip: energy +1
-        out[1] = thr_from_prob((1.0 - p->c) / p->c);  // down-flip
-        return 2;
-    }
-    const int z = 2 * p->dim;
-    const int ds_of[4] = {-2, -1, 1, 2};
-    size_t n = 0;
-    for (int di = 0; di < 4; ++di)
-        for (int nsum = -z; nsum <= z; ++nsum) {
-            const double dE = -(double)ds_of[di] * (p->J * (double)nsum + p->h);
-            out[n++] = thr_from_energy(dE, p->T);
-        }
-    return n;
 }
 
 }  // namespace host
@@ -196,23 +61,9 @@ void stat_sums(const sl_params* p, const sl_record& r, double nsites, double& bo
 
 }  // namespace
 
-struct sl_lattice {
-    sl_params params;
-    Layout lay;
-    uint8_t* base;
-    hipStream_t stream;
-    int kind;
-    uint64_t next_t;   // index of the next sweep
-    uint64_t pending;  // unread records
-    uint64_t first_t;  // t of the oldest unread record
-    int cur;           // copy of the lattice holding the current state
-    sl_launch launch;
-    uint64_t table[kMaxLut];
-    size_t table_n;
-    sl_record* stage;  // pinned host staging for record readback (record_capacity)
-};
 
-namespace {
+namespace spinlat {
+namespace rt {
 
 void release(sl_lattice* h)
 {
@@ -269,7 +120,6 @@ bool lut32_ok(const sl_lattice* h)
 // row, and shapes the whole-row kernels cannot take fall back to the window
 // kernels.
 constexpr uint64_t kResidentAuto = 16 * 1024;
-constexpr uint64_t kResidentChunk = 4096;
 
 sl_launch auto_launch(const sl_lattice* h)
 {
@@ -450,7 +300,82 @@ sl_status sweep_ne_sub(sl_lattice* h, uint64_t n)
     return SL_OK;
 }
 
-}  // namespace
+// Enqueue n sweeps (the caller has checked the count): the launches of the
+// lattice's schedule, records into ring slots pending .. pending + n - 1.
+sl_status enqueue_sweeps(sl_lattice* h, uint64_t n)
+{
+    if (is_sub_lattice(h->params.model)) return sweep_ne_sub(h, n);
+    SweepArgs a = args_of(h);
+    if (h->launch.mode == SL_MODE_RESIDENT) {
+        for (uint64_t i = 0; i < n;) {
+            const uint32_t k = (uint32_t)std::min<uint64_t>(n - i, kResidentChunk);
+            a.t = (uint32_t)(h->next_t + i);
+            a.acc = slot_ptr(h, h->pending + i);
+            hipError_t e = launch_resident(a, h->kind, k, h->stream);
+            if (e != hipSuccess) {
+                h->next_t += i;
+                h->pending += i;
+                return hip_fail(e, "resident sweep launch");
+            }
+            i += k;
+        }
+        h->next_t += n;
+        h->pending += n;
+        return SL_OK;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        a.t = (uint32_t)(h->next_t + i);
+        a.acc = slot_ptr(h, h->pending + i);
+        hipError_t e = hipSuccess;
+        const int H = h->launch.tile_rows, D = h->launch.tile_words;
+        switch (h->launch.mode) {
+            case SL_MODE_FUSED:
+            case SL_MODE_FUSED_WINDOW: {
+                const int nxt = h->cur ^ 1;
+                uint8_t* d0 = h->base + h->lay.off_col[nxt][0];
+                uint8_t* d1 = h->base + h->lay.off_col[nxt][1];
+                if (h->launch.mode == SL_MODE_FUSED)
+                    e = launch_row_fused(a, h->kind, H, D, a.col[0], a.col[1], d0, d1, h->stream);
+                else
+                    e = launch_fused_sweep(a, h->kind, a.col[0], a.col[1], d0, d1, h->stream);
+                if (e == hipSuccess) {
+                    h->cur = nxt;
+                    a.col[0] = d0;
+                    a.col[1] = d1;
+                }
+                break;
+            }
+            case SL_MODE_HALF:
+            case SL_MODE_HALF_WINDOW:
+                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
+                    a.colour = c;
+                    e = h->launch.mode == SL_MODE_HALF ? launch_row_half(a, h->kind, H, D, h->stream)
+                                                       : launch_tiled_half(a, h->kind, h->stream);
+                }
+                break;
+            default:
+                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
+                    a.colour = c;
+                    e = launch_simple_half(a, h->kind, h->stream);
+                }
+                break;
+        }
+        if (e != hipSuccess) {
+            // sweeps before i were enqueued and will produce their records
+            h->next_t += i;
+            h->pending += i;
+            return hip_fail(e, "sweep launch");
+        }
+    }
+    h->next_t += n;
+    h->pending += n;
+    return SL_OK;
+}
+
+}  // namespace rt
+}  // namespace spinlat
+
+using namespace spinlat::rt;
 
 extern "C" {
 
@@ -568,79 +493,10 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
 {
     if (!h) return fail(SL_E_INVALID, "NULL lattice");
     if (n == 0) return SL_OK;
-    if (h->pending + n > h->params.record_capacity)
-        return fail(SL_E_STATE, "%llu unread records + %llu sweeps exceed record_capacity %llu; "
-                                "call sl_measure first", (unsigned long long)h->pending,
-                    (unsigned long long)n, (unsigned long long)h->params.record_capacity);
-    const uint64_t t_end = sweep_limit(h->params.model);
-    if (h->next_t + n > t_end)
-        return fail(SL_E_OVERFLOW, "sweep index would reach %llu", (unsigned long long)t_end);
-    if (is_sub_lattice(h->params.model)) return sweep_ne_sub(h, n);
-    SweepArgs a = args_of(h);
-    if (h->launch.mode == SL_MODE_RESIDENT) {
-        for (uint64_t i = 0; i < n;) {
-            const uint32_t k = (uint32_t)std::min<uint64_t>(n - i, kResidentChunk);
-            a.t = (uint32_t)(h->next_t + i);
-            a.acc = slot_ptr(h, h->pending + i);
-            hipError_t e = launch_resident(a, h->kind, k, h->stream);
-            if (e != hipSuccess) {
-                h->next_t += i;
-                h->pending += i;
-                return hip_fail(e, "resident sweep launch");
-            }
-            i += k;
-        }
-        h->next_t += n;
-        h->pending += n;
-        return SL_OK;
-    }
-    for (uint64_t i = 0; i < n; ++i) {
-        a.t = (uint32_t)(h->next_t + i);
-        a.acc = slot_ptr(h, h->pending + i);
-        hipError_t e = hipSuccess;
-        const int H = h->launch.tile_rows, D = h->launch.tile_words;
-        switch (h->launch.mode) {
-            case SL_MODE_FUSED:
-            case SL_MODE_FUSED_WINDOW: {
-                const int nxt = h->cur ^ 1;
-                uint8_t* d0 = h->base + h->lay.off_col[nxt][0];
-                uint8_t* d1 = h->base + h->lay.off_col[nxt][1];
-                if (h->launch.mode == SL_MODE_FUSED)
-                    e = launch_row_fused(a, h->kind, H, D, a.col[0], a.col[1], d0, d1, h->stream);
-                else
-                    e = launch_fused_sweep(a, h->kind, a.col[0], a.col[1], d0, d1, h->stream);
-                if (e == hipSuccess) {
-                    h->cur = nxt;
-                    a.col[0] = d0;
-                    a.col[1] = d1;
-                }
-                break;
-            }
-            case SL_MODE_HALF:
-            case SL_MODE_HALF_WINDOW:
-                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
-                    a.colour = c;
-                    e = h->launch.mode == SL_MODE_HALF ? launch_row_half(a, h->kind, H, D, h->stream)
-                                                       : launch_tiled_half(a, h->kind, h->stream);
-                }
-                break;
-            default:
-                for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
-                    a.colour = c;
-                    e = launch_simple_half(a, h->kind, h->stream);
-                }
-                break;
-        }
-        if (e != hipSuccess) {
-            // sweeps before i were enqueued and will produce their records
-            h->next_t += i;
-            h->pending += i;
-            return hip_fail(e, "sweep launch");
-        }
-    }
-    h->next_t += n;
-    h->pending += n;
-    return SL_OK;
+    sl_status st = check_sweep_count(h->pending, h->params.record_capacity, h->next_t,
+                                     sweep_limit(h->params.model), n);
+    if (st != SL_OK) return st;
+    return enqueue_sweeps(h, n);
 }
 
 sl_status sl_measure(sl_lattice* h, sl_record* out, size_t cap, size_t* n_out)
@@ -818,6 +674,6 @@ const char* sl_status_str(sl_status s)
     return "SL_E_UNKNOWN";
 }
 
-const char* sl_last_error(void) { return g_err; }
+const char* sl_last_error(void) { return last_error(); }
 
 }  // extern "C"

@@ -3,20 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_logic.h"
+
 namespace spinlat {
 
-// Per-record accumulators: kSub sub-slots spread the workgroups' atomics, each
-// on a 128-byte line of its own (atomics on one line serialise: with the four
-// sub-slots of a line shared by 2048 workgroups a launch took 7.4 us instead
-// of 2.3 us); a sub-slot holds kQ int64 quantities.
-constexpr int kSub = 16;
-constexpr int kQ = 4;           // bond_sum, mag, accepted, unflipped
-constexpr int kSubStride = 16;  // int64 words per sub-slot (one 128-byte line)
-constexpr int kSlotWords = kSub * kSubStride;
-constexpr int kRecordWords = 5;  // t, bond_sum, mag, accepted, unflipped
-constexpr int kMaxLut = 64;      // >= 4*(4*3+1) = 52 Ising entries
-
-enum Kind : int { KIND_ISING_HALF = 0, KIND_ISING_ONE = 1, KIND_NE = 2 };
+// Record accumulator layout (kSub, kQ, kSubStride, kSlotWords, kRecordWords),
+// kMaxLut and the kernel kinds come from host_logic.h.
 
 // Geometry of the colour-split layout.  Natural site (x, y, z) has colour
 // (x+y+z)&1 and in-colour index k = ((z*L + y)*L + x) >> 1; the colour array
@@ -93,9 +85,7 @@ struct NeSubArgs {
                                 // unflipped of the launch-start lattice
 };
 
-// B in {8, 16, 32, 64}, L % B == 0, lambda a power of two in [2, 128],
-// 2 lambda <= B^2 (balanced variant: 8 lambda <= B^2).
-bool ne_sub_supported(uint32_t L, int B, int lambda, bool balanced);
+// Shapes: host::ne_sub_supported.
 // balanced: colour 0 then colour 1 per iteration, P/(8 lambda) iterations
 // (four launches per sweep); else q = P/(2 lambda) iterations (two launches)
 hipError_t launch_ne_sub(const NeSubArgs& a, int B, int lambda, bool balanced, hipStream_t s);

@@ -145,6 +145,14 @@ def _check(status: int) -> None:
         raise SpinlatError(status, lib().sl_last_error().decode())
 
 
+def _count(n) -> int:
+    """A sweep count as the C ABI's uint64 (ctypes would wrap a negative one)."""
+    n = int(n)
+    if n < 0 or n >= 2 ** 64:
+        raise ValueError(f"sweep count {n} is outside [0, 2^64)")
+    return n
+
+
 @dataclass
 class Params:
     """Model parameters (paper Sec. 3): Ising (J, h, T; spin-1/2 or spin-1; 2D or
@@ -245,7 +253,7 @@ class Lattice:
 
     # -- the hot path -------------------------------------------------------
     def sweep(self, n: int) -> None:
-        _check(lib().sl_sweep(self._h, int(n)))
+        _check(lib().sl_sweep(self._h, _count(n)))
 
     def counts(self):
         p, t = ctypes.c_uint64(), ctypes.c_uint64()
@@ -393,7 +401,8 @@ class Batch:
         self.params = {}
 
     def add(self, p: Params, sweeps: int, init_spins=None):
-        """Job id, or None when the arena has no room for it."""
+        """Job id, or None when the arena has no room for it or the job table
+        is full (both free up as jobs are removed)."""
         torch = self._torch
         ptr = 0
         if p.init == INIT_BUFFER:
@@ -401,15 +410,15 @@ class Batch:
             ptr = t.data_ptr()
         cp = p.c_struct(ptr)
         jid = ctypes.c_uint32()
-        st = lib().sl_batch_add(self._h, ctypes.byref(cp), int(sweeps), ctypes.byref(jid))
-        if st == 3:
+        st = lib().sl_batch_add(self._h, ctypes.byref(cp), _count(sweeps), ctypes.byref(jid))
+        if st in (3, 5):  # SL_E_BUFFER: no arena room; SL_E_STATE: job table full
             return None
         _check(st)
         self.params[jid.value] = p
         return jid.value
 
     def sweep(self, n: int) -> None:
-        _check(lib().sl_batch_sweep(self._h, int(n)))
+        _check(lib().sl_batch_sweep(self._h, _count(n)))
 
     def status(self, job: int):
         d, r, p = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

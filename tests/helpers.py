@@ -42,3 +42,63 @@ def run_gpu(sp: S.Params, nsweeps: int, launch=None, chunks=None, init_spins=Non
     spins = lat.spins()
     lat.close()
     return spins, np.vstack(recs)
+
+
+# ---------------------------------------------------------------------------
+# Which launch schedules the library must accept for a shape (include/spinlat.h,
+# sl_set_launch): a refusal outside these rules, or an acceptance inside a
+# refusal, is a failure, never a skip.
+
+RESIDENT_MAX_BYTES = 48 * 1024  # both colours of the lattice in one workgroup's LDS
+
+
+def _row_fits(sp: S.Params, H: int, D: int, fused: bool) -> bool:
+    """Whole-row kernels: a colour row of L/8 words splits into row groups of
+    R = L/(8D) lanes, R <= 64 or a multiple of 64 up to 1024; FUSED is 2D."""
+    if D not in (1, 2, 4) or H < 1 or (fused and sp.dim != 2):
+        return False
+    ncols = sp.L // 8
+    if ncols % D:
+        return False
+    R = ncols // D
+    return R <= 64 or (R % 64 == 0 and R <= 1024)
+
+
+def expected_supported(sp: S.Params, launch) -> bool:
+    mode, H, D = launch
+    if sp.model in (S.NE_SUBLATTICE, S.NE_SUBLATTICE_BALANCED):
+        return mode == S.MODE_AUTO
+    if mode in (S.MODE_AUTO, S.MODE_SIMPLE):
+        return True
+    if mode == S.MODE_RESIDENT:
+        return H == 0 and D == 0 and sp.nsites <= RESIDENT_MAX_BYTES
+    spin_half_table = (sp.model == S.ISING and sp.two_s == 1) or sp.model == S.NE_COUPLED
+    if mode in (S.MODE_HALF, S.MODE_FUSED):
+        if spin_half_table and 0 in S.threshold_table(sp):
+            return False  # the 32-bit "word <= thr - 1" table needs every threshold >= 1
+        fused = mode == S.MODE_FUSED
+        H = H or 8
+        if D == 0:
+            D = next((d for d in (2, 4, 1) if _row_fits(sp, H, d, fused)), 2)
+        return _row_fits(sp, H, D, fused)
+    if mode in (S.MODE_HALF_WINDOW, S.MODE_FUSED_WINDOW):
+        if sp.model == S.NE_COUPLED:
+            return False
+        if D != 0 or H < 0 or H > sp.L:
+            return False
+        return mode == S.MODE_HALF_WINDOW or sp.dim == 2
+    raise ValueError(f"unknown mode {mode}")
+
+
+def assert_refused(sp: S.Params, launch) -> None:
+    """The schedule must be refused with SL_E_UNSUPPORTED."""
+    lat = S.Lattice(sp)
+    try:
+        try:
+            lat.set_launch(*launch)
+        except S.SpinlatError as e:
+            assert e.status == 2, e
+            return
+        raise AssertionError(f"schedule {launch} was accepted for {sp}")
+    finally:
+        lat.close()

@@ -205,3 +205,12 @@ def test_autocorrelation_equals_oracle():
             assert S.autocorrelation(p, ov) == pytest.approx(OB.autocorrelation(op, ov), rel=1e-15)
     with pytest.raises(S.SpinlatError):
         S.autocorrelation(S.Params(), 10)
+
+
+def test_sweep_counts_are_checked_before_the_abi():
+    """A negative or oversized count would wrap in the C uint64: the binding
+    refuses it (the library's own overflow-safe checks are in host_checks.cpp)."""
+    assert B._count(0) == 0 and B._count(2 ** 64 - 1) == 2 ** 64 - 1
+    for bad in (-1, -(2 ** 63), 2 ** 64):
+        with pytest.raises(ValueError):
+            B._count(bad)
