@@ -30,9 +30,13 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 ALGO_BYTES_PER_ATTEMPT = 2   # one int8 read + one int8 write per site per sweep
 VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4  # 3.93e13 32-bit lane-ops/s in wave64 instructions
 # sources of the profiled kernels, hashed into profiles/traffic.json
+ROW_SOURCES = ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
+               "spinlat_internal.h", "host_logic.h")
 KERNEL_SOURCES = {
-    "ising2d_L8192": ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
-                      "spinlat_internal.h", "host_logic.h"),
+    "ising2d_L8192": ROW_SOURCES,
+    "ising3d_L256_s12": ROW_SOURCES,
+    "ising3d_L256_s1": ROW_SOURCES,
+    "ne2d_L4096": ROW_SOURCES,
     "ne2d_sub_L4096": ("ne_sub_device.hpp", "philox.hpp", "spinlat_internal.h", "host_logic.h"),
 }
 

@@ -105,10 +105,11 @@ def test_resident_chunks_and_mixed_modes():
     lat.close()
 
 
-@pytest.mark.parametrize("kw", [dict(L=216, T=2.3), dict(dim=3, L=36, two_s=2, T=3.0),
+@pytest.mark.parametrize("kw", [dict(L=216, T=2.3), dict(dim=3, L=32, two_s=2, T=3.0),
                                 dict(model=S.NORTH_EAST, L=216, c=0.35)])
 def test_resident_largest_lattices(kw):
-    """Lattices of 46656 sites (2D L = 216, 3D L = 36), the largest under the 48 KiB limit."""
+    """The largest lattices under the 48 KiB limit with L % 8 == 0: 2D L = 216
+    (46656 sites), 3D L = 32 (32768 sites)."""
     sp = S.Params(seed=31, record_capacity=32, **kw)
     _check(sp, 20, launch=RESIDENT)
 
