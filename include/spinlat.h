@@ -376,6 +376,27 @@ sl_status sl_overlap(sl_lattice* lat, const int8_t* reference, int64_t* overlap)
  * Phi should decay to 0.  SL_E_INVALID for Ising parameters. */
 sl_status sl_autocorrelation(const sl_params* params, int64_t overlap, double* phi);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sl_create_lattice +
+ * sl_sweep(n) + sl_measure + sl_copy_spins of one lattice in one call that
+ * calls no allocator, host or device.  The working memory (two copies of the
+ * colour arrays, the record accumulators and the threshold table) is a
+ * static device array of 33 MiB that each GPU the library runs on holds until
+ * the process ends; lattices of up to 2^24 sites fit (e.g. 2D 4096^2, 3D 256^3),
+ * larger ones return SL_E_UNSUPPORTED.  params as for sl_create_lattice
+ * (record_capacity is ignored; SL_INIT_BUFFER reads init_spins, which may be
+ * spins_out).  On the stream (a hipStream_t, NULL: the default stream) it
+ * initialises the lattice, runs sweeps t0 .. t0 + n - 1 in the default
+ * schedule, writes the final lattice to spins_out (device, L^dim bytes,
+ * natural order as sl_copy_spins) and the records r_0 .. r_n to records_out
+ * (device, n + 1 records).  Asynchronous: the outputs are valid once the
+ * stream has reached this work.  Calls on one GPU share its working memory:
+ * calls that overlap on one GPU (other streams, other threads) race.
+ * Errors as sl_create_lattice and sl_sweep; SL_E_BUFFER if an output is NULL. */
+sl_status sl_sweep_static(const sl_params* params, uint64_t n, int8_t* spins_out,
+                          sl_record* records_out, void* hip_stream);
+
 const char* sl_status_str(sl_status status);
 const char* sl_last_error(void);
 

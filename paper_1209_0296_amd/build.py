@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libspinlat.so")
 SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "kernels_row.hip", "kernels_batch.hip",
            "kernels_ne_sub.hip", "kernels_ne_sub_b8.hip", "kernels_ne_sub_b16.hip",
            "kernels_ne_sub_b32.hip", "kernels_ne_sub_b64.hip", "host_logic.cpp", "runtime.cpp",
-           "batch.cpp"]
+           "batch.cpp", "static_sweep.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -33,7 +33,7 @@ EXPORTS = (
     "sl_record_observables", "sl_batch_job_bytes", "sl_batch_base_bytes", "sl_batch_create",
     "sl_batch_add", "sl_batch_sweep", "sl_batch_job_status", "sl_batch_measure",
     "sl_batch_copy_spins", "sl_batch_remove", "sl_batch_destroy", "sl_batch_drain",
-    "sl_record_statistics", "sl_overlap", "sl_autocorrelation",
+    "sl_record_statistics", "sl_overlap", "sl_autocorrelation", "sl_sweep_static",
 )
 
 
@@ -132,6 +132,7 @@ def lib():
     L.sl_record_statistics.argtypes = [P, ctypes.c_void_p, sz, ctypes.POINTER(CStats)]
     L.sl_overlap.argtypes = [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
     L.sl_autocorrelation.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    L.sl_sweep_static.argtypes = [P, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sl_status_str", "sl_last_error"):
