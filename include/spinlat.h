@@ -161,16 +161,23 @@ typedef enum sl_mode {
                                  with the colour-0 halo rows recomputed (2D only) */
     SL_MODE_HALF_WINDOW = 4,  /* as HALF with 64-lane column windows (any shape) */
     SL_MODE_FUSED_WINDOW = 5, /* as FUSED with 64-lane column windows and halo lanes */
-    SL_MODE_RESIDENT = 6      /* small lattices (both colours <= 48 KiB): one workgroup keeps
+    SL_MODE_RESIDENT = 6,     /* small lattices (both colours <= 48 KiB): one workgroup keeps
                                  the lattice in LDS and runs up to 4096 whole sweeps per
                                  launch; the default for lattices of at most 16 KiB */
+    SL_MODE_HALF_ROWS = 7     /* one colour per launch, two launches per sweep; every colour
+                                 row is updated by its own row group from vector loads of
+                                 its neighbour rows, no walk; tile_rows = waves per
+                                 workgroup, 1..16 (0: 4), tile_words D in {1, 2, 4} (0:
+                                 widest that fits); the colour row must fit one wave:
+                                 L / (8 D) <= 64.  The default for 3D lattices that fit */
 } sl_mode;
 
 typedef struct sl_launch {
     int32_t mode;        /* sl_mode */
-    int32_t tile_rows;   /* streaming modes: rows per strip (0: default) */
-    int32_t tile_words;  /* HALF/FUSED: 4-byte words per lane, 1, 2 or 4 (0: default);
-                            must be 0 for the window modes */
+    int32_t tile_rows;   /* streaming modes: rows per strip; HALF_ROWS: waves per
+                            workgroup (0: default) */
+    int32_t tile_words;  /* HALF/FUSED/HALF_ROWS: 4-byte words per lane, 1, 2 or 4 (0:
+                            default); must be 0 for the window modes */
     int32_t reserved;
 } sl_launch;
 

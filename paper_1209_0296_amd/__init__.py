@@ -8,7 +8,7 @@ hand-written HIP kernels behind the C ABI of ``include/spinlat.h``.
 """
 from .spinlat import (  # noqa: F401
     ABI_VERSION, EXPORTS, INIT_BUFFER, INIT_COLD, INIT_RANDOM, ISING, MODE_AUTO, MODE_FUSED,
-    MODE_HALF, MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT, MODE_SIMPLE, NORTH_EAST,
+    MODE_HALF, MODE_HALF_ROWS, MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT, MODE_SIMPLE, NORTH_EAST,
     NE_COUPLED, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, RECORD_DTYPE, Lattice, Params, SpinlatError, lib,
     query_bytes, records_to_array, threshold_table, Batch, batch_config, batch_job_bytes,
     batch_base_bytes, record_statistics, autocorrelation,

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 from dataclasses import replace
 
-from .spinlat import (MODE_FUSED, MODE_FUSED_WINDOW, MODE_HALF, MODE_HALF_WINDOW, MODE_RESIDENT,
+from .spinlat import (MODE_FUSED, MODE_FUSED_WINDOW, MODE_HALF, MODE_HALF_ROWS, MODE_HALF_WINDOW, MODE_RESIDENT,
                       MODE_SIMPLE, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, Lattice, Params,
                       SpinlatError)
 
@@ -29,6 +29,9 @@ def candidates(p: Params):
         for H in (2, 4, 8, 16):
             for D in (1, 2, 4):
                 out.append((mode, H, D))
+    for waves in (4, 16):
+        for D in (1, 2, 4):
+            out.append((MODE_HALF_ROWS, waves, D))
     out.append((MODE_HALF_WINDOW, 0, 0))
     if p.dim == 2:
         out.append((MODE_FUSED_WINDOW, 0, 0))

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libspinlat.so")
 SOURCES = ["kernels_simple.hip", "kernels_stream.hip", "kernels_row.hip", "kernels_batch.hip",
            "kernels_ne_sub.hip", "kernels_ne_sub_b8.hip", "kernels_ne_sub_b16.hip",
            "kernels_ne_sub_b32.hip", "kernels_ne_sub_b64.hip", "host_logic.cpp", "runtime.cpp",
-           "batch.cpp", "static_sweep.hip"]
+           "batch.cpp", "static_sweep.hip", "kernels_rows.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -27,26 +27,33 @@ FLAGS = [
 ]
 
 
-def _headers_mtime() -> float:
-    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".hpp"))]
-    paths.append(os.path.join(ROOT, "include", "spinlat.h"))
-    return max(os.path.getmtime(p) for p in paths)
+def _deps_mtime(path: str, seen=None) -> float:
+    """Newest modification time of a source and the local headers it includes."""
+    import re
+
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return 0.0
+    seen.add(path)
+    t = os.path.getmtime(path)
+    with open(path) as fh:
+        for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), flags=re.M):
+            t = max(t, _deps_mtime(os.path.normpath(os.path.join(os.path.dirname(path), inc)), seen))
+    return t
 
 
 def build(verbose: bool = True, incremental: bool = False) -> str:
     """Compile every source and link the shared library.  By default every
     object is rebuilt; with incremental=True only objects older than their
-    source or any header are."""
+    source or a local header it includes are."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    hdr = _headers_mtime() if incremental else 0.0
     cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         path = os.path.join(CSRC, src)
-        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(
-                hdr, os.path.getmtime(path)):
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(path):
             continue
         cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
         if src.endswith(".cpp"):

@@ -56,6 +56,13 @@ __device__ __forceinline__ uint32_t wrapr(int y, uint32_t L)
     return (uint32_t)(r < 0 ? r + (int)L : r);
 }
 
+// Periodic row index for y in [-L, 2L): the walks step at most a few rows
+// past an edge, so two compares replace the integer division of wrapr.
+__device__ __forceinline__ uint32_t wrap1(int y, uint32_t L)
+{
+    return (uint32_t)(y < 0 ? y + (int)L : (y >= (int)L ? y - (int)L : y));
+}
+
 __device__ __forceinline__ uint32_t remap_block()
 {
     const uint32_t nb = gridDim.x;
@@ -535,11 +542,11 @@ __device__ __forceinline__ void fused_step(int i, FusedState<KIND, D>& st, const
     const uint32_t L = rg.L;
     const uint64_t rowb = rg.Lh;
     const uint64_t cb = 4ull * D * ln.pos;
-    const uint32_t yi = wrapr(i, L);
+    const uint32_t yi = wrap1(i, L);
     if constexpr (PREF) {
         // for step i+1: old colour-1 row i+2, old colour-0 row i+1
-        st.c1n = ldv<D>(S1, (uint64_t)wrapr(i + 2, L) * rowb + cb);
-        st.own0n = ldv<D>(S0, (uint64_t)wrapr(i + 1, L) * rowb + cb);
+        st.c1n = ldv<D>(S1, (uint64_t)wrap1(i + 2, L) * rowb + cb);
+        st.own0n = ldv<D>(S0, (uint64_t)wrap1(i + 1, L) * rowb + cb);
     }
     uint32_t e0 = 0, e1 = 0;
     if constexpr (XW) {
@@ -579,7 +586,7 @@ __device__ __forceinline__ void fused_step(int i, FusedState<KIND, D>& st, const
     const Vec<D> q0 = prepv<KIND, D>(new0);
     if constexpr (DO_C1) {
         // colour 1, row i-1 (parity of i as well): neighbours new colour-0 rows i-2, i-1, i
-        const uint32_t ym = wrapr(i - 1, L);
+        const uint32_t ym = wrap1(i - 1, L);
         const uint32_t x1 = shift_in<XW, P>(st.q0b.w[D - 1], st.q0b.w[0], ln, e1);
         uint32_t side1[D];
         side_words<D, P>(st.q0b, x1, side1);

@@ -106,15 +106,15 @@ bool lut32_ok(const sl_lattice* h)
 // Default schedule for a shape, from the schedule autotuner's timings on
 // MI355X (us per sweep):
 //   - lattices of at most 16 KiB run resident in LDS (2D L = 64: 2.4);
-//   - 2D up to L = 2048: fused with 2-row strips, 1 word per lane up to
-//     L = 512, else 2 (L = 256: 5.8; 1024: 6.2; 2048: 8.1; the direct kernel
-//     takes 8.5 at these sizes);
-//   - 2D L = 4096: fused, 4-row strips (spin-1/2 16.4 with D 4; spin-1 and NE
-//     D 2); from L = 8192 spin-1/2 takes 8-row strips with D 4 (42.9 at 8192)
-//     and 16-row strips from L = 16384 (625 at 32768); NE keeps H 4 D 2;
-//   - 3D up to L = 160: half-sweeps with 2-row strips, 1 word per lane (L = 128:
-//     10.3 against 14.1 with 4-row strips and D 4); larger: 4-row strips, D 4
-//     (L = 256: 19.3).
+//   - 2D up to L = 1024: fused with 2-row strips, 1 word per lane (L = 1024:
+//     4.9 against 6.1 with 2 words); L = 2048: fused, 2-row strips, 2 words;
+//   - 2D L = 4096: fused, 4-row strips, 2 words (spin-1/2: 14.6 against 17.7
+//     with 4 words); from L = 8192 spin-1/2 takes 8-row strips with 4 words
+//     (41.5 at 8192: the unrolled walk) and 16-row strips from L = 16384;
+//     spin-1 and NE keep 4-row strips with 2 words;
+//   - 3D: half-sweeps by independent row groups, 4 words per lane from L = 128
+//     (L = 256: 18.4 against 19.2 for the walk with 4-row strips; L = 128: 8.8
+//     against 10.6), 1 word below (L = 64: 7.5 against 8.9).
 // A fused 3D sweep would recompute a halo in two directions, so 3D uses
 // half-sweeps.  Other widths are tried in order when D does not divide the
 // row, and shapes the whole-row kernels cannot take fall back to the window
@@ -137,29 +137,39 @@ sl_launch auto_launch(const sl_lattice* h)
         return r;
     }
     const int L = h->params.L;
-    const bool fused = h->params.dim == 2;
     const bool half_spin = h->kind == KIND_ISING_HALF;
+    sl_launch l{};
+    if (h->params.dim == 3) {
+        const int Ds[3] = {L >= 128 ? 4 : 1, 2, L >= 128 ? 1 : 4};
+        for (int D : Ds)
+            if (rows_supported(g, h->kind, 4, D, lut32_ok(h))) {
+                l.mode = SL_MODE_HALF_ROWS;
+                l.tile_rows = 4;
+                l.tile_words = D;
+                return l;
+            }
+    }
+    const bool fused = h->params.dim == 2;
     int H = 4, Ds[3] = {4, 2, 1};
     if (h->params.dim == 3) {
         if (L <= 160) {
             H = 2;
             Ds[0] = 1, Ds[1] = 2, Ds[2] = 4;
         }
-    } else if (L <= 512) {
+    } else if (L <= 1024) {
         H = 2;
         Ds[0] = 1, Ds[1] = 2, Ds[2] = 4;
     } else if (L <= 2048) {
         H = 2;
         Ds[0] = 2, Ds[1] = 1, Ds[2] = 4;
-    } else if (!half_spin) {
-        H = (h->kind == KIND_NE || L < 8192) ? 4 : 8;
+    } else if (!half_spin || L < 8192) {
+        H = 4;
         Ds[0] = 2, Ds[1] = 4, Ds[2] = 1;
     } else if (L >= 16384) {
         H = 16;
-    } else if (L >= 8192) {
+    } else {
         H = 8;
     }
-    sl_launch l{};
     for (int D : Ds)
         if (row_supported(g, h->kind, H, D, fused, lut32_ok(h))) {
             l.mode = fused ? SL_MODE_FUSED : SL_MODE_HALF;
@@ -183,10 +193,11 @@ sl_status check_launch(const sl_lattice* h, sl_launch* l)
     const Geom g = {(uint32_t)h->params.L, (uint32_t)(h->params.L / 2), (uint32_t)h->params.dim,
                     0u, h->lay.nh};
     if (h->params.model == SL_NE_COUPLED) {
-        const bool row = l->mode == SL_MODE_HALF || l->mode == SL_MODE_FUSED;
+        const bool row = l->mode == SL_MODE_HALF || l->mode == SL_MODE_FUSED || l->mode == SL_MODE_HALF_ROWS;
         if (!(l->mode == SL_MODE_SIMPLE || l->mode == SL_MODE_RESIDENT || (row && lut32_ok(h))))
             return fail(SL_E_UNSUPPORTED, "coupled NE lattices run SL_MODE_SIMPLE, SL_MODE_RESIDENT, "
-                                          "or SL_MODE_HALF / SL_MODE_FUSED when every threshold is >= 1");
+                                          "or SL_MODE_HALF / SL_MODE_FUSED / SL_MODE_HALF_ROWS when every "
+                                          "threshold is >= 1");
     }
     switch (l->mode) {
         case SL_MODE_SIMPLE:
@@ -214,6 +225,18 @@ sl_status check_launch(const sl_lattice* h, sl_launch* l)
                             "this lattice", l->mode, l->tile_rows, l->tile_words);
             return SL_OK;
         }
+        case SL_MODE_HALF_ROWS:
+            if (l->tile_rows == 0) l->tile_rows = 4;
+            if (l->tile_words == 0)
+                for (int D : {4, 2, 1})
+                    if (rows_supported(g, h->kind, l->tile_rows, D, lut32_ok(h))) {
+                        l->tile_words = D;
+                        break;
+                    }
+            if (!rows_supported(g, h->kind, l->tile_rows, l->tile_words, lut32_ok(h)))
+                return fail(SL_E_UNSUPPORTED, "SL_MODE_HALF_ROWS with %d waves per workgroup and %d words "
+                            "per lane does not fit this lattice", l->tile_rows, l->tile_words);
+            return SL_OK;
         case SL_MODE_HALF_WINDOW:
         case SL_MODE_FUSED_WINDOW:
             if (!tiled_supported(g, h->kind, l->tile_rows, l->tile_words,
@@ -347,10 +370,12 @@ sl_status enqueue_sweeps(sl_lattice* h, uint64_t n)
             }
             case SL_MODE_HALF:
             case SL_MODE_HALF_WINDOW:
+            case SL_MODE_HALF_ROWS:
                 for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
                     a.colour = c;
-                    e = h->launch.mode == SL_MODE_HALF ? launch_row_half(a, h->kind, H, D, h->stream)
-                                                       : launch_tiled_half(a, h->kind, h->stream);
+                    if (h->launch.mode == SL_MODE_HALF) e = launch_row_half(a, h->kind, H, D, h->stream);
+                    else if (h->launch.mode == SL_MODE_HALF_ROWS) e = launch_rows_half(a, h->kind, H, D, h->stream);
+                    else e = launch_tiled_half(a, h->kind, h->stream);
                 }
                 break;
             default:

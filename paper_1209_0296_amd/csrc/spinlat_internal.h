@@ -65,6 +65,11 @@ bool tiled_supported(const Geom& g, int kind, int tile_rows, int tile_words, boo
 // lane D in {1, 2, 4}; spin-1/2 needs every threshold >= 1 (lut32_ok).
 bool row_supported(const Geom& g, int kind, int tile_rows, int tile_words, bool fused, bool lut32_ok);
 hipError_t launch_row_half(const SweepArgs& a, int kind, int H, int D, hipStream_t s);
+// Half-sweep by independent row groups (no walk): workgroups of `waves`
+// waves (1..16), D in {1, 2, 4} words per lane, a colour row within one wave;
+// spin-1/2 needs every threshold >= 1.
+bool rows_supported(const Geom& g, int kind, int waves, int tile_words, bool lut32_ok);
+hipError_t launch_rows_half(const SweepArgs& a, int kind, int waves, int D, hipStream_t s);
 hipError_t launch_row_fused(const SweepArgs& a, int kind, int H, int D, const uint8_t* src0,
                             const uint8_t* src1, uint8_t* dst0, uint8_t* dst1, hipStream_t s);
 

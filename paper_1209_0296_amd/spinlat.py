@@ -21,7 +21,7 @@ ABI_VERSION = 2
 ISING, NORTH_EAST, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, NE_COUPLED = 0, 1, 2, 3, 4
 INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
 MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
-MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT = 4, 5, 6
+MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT, MODE_HALF_ROWS = 4, 5, 6, 7
 STATUS = {0: "SL_OK", 1: "SL_E_INVALID", 2: "SL_E_UNSUPPORTED", 3: "SL_E_BUFFER",
           4: "SL_E_HIP", 5: "SL_E_STATE", 6: "SL_E_OVERFLOW"}
 

@@ -81,6 +81,15 @@ def expected_supported(sp: S.Params, launch) -> bool:
         if D == 0:
             D = next((d for d in (2, 4, 1) if _row_fits(sp, H, d, fused)), 2)
         return _row_fits(sp, H, D, fused)
+    if mode == S.MODE_HALF_ROWS:
+        if spin_half_table and 0 in S.threshold_table(sp):
+            return False
+        if H < 0 or H > 16:
+            return False
+        ncols = sp.L // 8
+        if D == 0:
+            D = next((d for d in (4, 2, 1) if ncols % d == 0 and ncols // d <= 64), 4)
+        return D in (1, 2, 4) and ncols % D == 0 and ncols // D <= 64
     if mode in (S.MODE_HALF_WINDOW, S.MODE_FUSED_WINDOW):
         if sp.model == S.NE_COUPLED:
             return False

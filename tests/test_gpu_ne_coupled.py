@@ -18,7 +18,7 @@ RESIDENT = (S.MODE_RESIDENT, 0, 0)
 AUTO = (S.MODE_AUTO, 0, 0)
 # whole-row kernels: (mode, rows per strip, words per lane)
 ROW = [(S.MODE_FUSED, 0, 0), (S.MODE_HALF, 0, 0), (S.MODE_FUSED, 3, 1), (S.MODE_FUSED, 8, 2),
-       (S.MODE_HALF, 5, 4)]
+       (S.MODE_HALF, 5, 4), (S.MODE_FUSED, 4, 2), (S.MODE_HALF_ROWS, 0, 0), (S.MODE_HALF_ROWS, 0, 1)]
 
 RATES = [dict(J=1.0, h=0.0, T=2.269, c=0.5), dict(J=1.0, h=0.3, T=2.0, c=0.6),
          dict(J=-0.7, h=0.2, T=1.5, c=0.4), dict(J=0.5, h=-1.1, T=math.inf, c=0.3)]

@@ -19,6 +19,9 @@ AUTO = (S.MODE_AUTO, 0, 0)
 RESIDENT = (S.MODE_RESIDENT, 0, 0)
 # whole-row kernels: (mode, rows per strip, words per lane)
 ROW = [(m, H, D) for m in (S.MODE_HALF, S.MODE_FUSED) for H, D in ((3, 1), (8, 2), (5, 4))]
+# whole-row walks with the unrolled strip heights, and row groups without a walk
+ROW += [(S.MODE_FUSED, 2, 4), (S.MODE_FUSED, 4, 2), (S.MODE_FUSED, 8, 4), (S.MODE_HALF_ROWS, 0, 0),
+        (S.MODE_HALF_ROWS, 1, 1), (S.MODE_HALF_ROWS, 3, 2), (S.MODE_HALF_ROWS, 16, 4)]
 
 
 def _check(sp, nsweeps, launch=None, chunks=None, nthreads=0):
@@ -70,7 +73,9 @@ def test_strip_heights(rows, mode):
 @pytest.mark.parametrize("L", [8, 16, 24, 40, 64, 128])
 @pytest.mark.parametrize("two_s", [1, 2])
 @pytest.mark.parametrize("launch", [SIMPLE, HALF_W, (S.MODE_HALF_WINDOW, 5, 0), AUTO, RESIDENT,
-                                    (S.MODE_HALF, 3, 1), (S.MODE_HALF, 8, 2), (S.MODE_HALF, 4, 4)])
+                                    (S.MODE_HALF, 3, 1), (S.MODE_HALF, 8, 2), (S.MODE_HALF, 4, 4),
+                                    (S.MODE_HALF_ROWS, 1, 1), (S.MODE_HALF_ROWS, 3, 2),
+                                    (S.MODE_HALF_ROWS, 0, 4), (S.MODE_HALF_ROWS, 16, 4)])
 def test_ising3d_shapes(L, two_s, launch):
     sp = S.Params(dim=3, L=L, two_s=two_s, T=4.5 if two_s == 1 else 3.2, seed=3 + L,
                   record_capacity=64)
