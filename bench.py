@@ -32,10 +32,12 @@ VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4  # 3.93e13 32-bit lane-ops/s in wave
 # sources of the profiled kernels, hashed into profiles/traffic.json
 ROW_SOURCES = ("kernels_row.hip", "row_device.hpp", "site_update.hpp", "philox.hpp",
                "spinlat_internal.h", "host_logic.h")
+ROWS_SOURCES = ("kernels_rows.hip", "rows_device.hpp", "row_device.hpp", "site_update.hpp", "philox.hpp",
+                "spinlat_internal.h", "host_logic.h")
 KERNEL_SOURCES = {
     "ising2d_L8192": ROW_SOURCES,
-    "ising3d_L256_s12": ROW_SOURCES,
-    "ising3d_L256_s1": ROW_SOURCES,
+    "ising3d_L256_s12": ROWS_SOURCES,
+    "ising3d_L256_s1": ROWS_SOURCES,
     "ne2d_L4096": ROW_SOURCES,
     "ne2d_sub_L4096": ("ne_sub_device.hpp", "philox.hpp", "spinlat_internal.h", "host_logic.h"),
 }
@@ -191,37 +193,70 @@ def cpu_baseline(cfg, sweeps, threads, single_sweeps=2):
 
 
 def served(args):
-    """Continuous batching of a Poisson stream of independent Ising jobs, and
-    the same first jobs as a closed batch, batched vs one run per launch."""
+    """Continuous batching of a Poisson stream of independent Ising jobs.
+
+    1. The batch autotuner picks the strip height and chunk size on a sample
+       of the stream (closed batch).
+    2. Capacity: the whole stream as a closed batch (every job waiting at time
+       0): jobs/s and attempts/s at saturation.
+    3. Latency: the stream offered at 70% of that capacity (Poisson arrivals,
+       served in real time): p50/p99 of completion - arrival.
+    4. The first `compare_jobs` jobs as a closed batch, batched vs one lattice
+       per launch, with identical records; and batched without graph replay."""
     import numpy as np
 
+    from paper_1209_0296_amd import BATCH_NO_GRAPH
+    from paper_1209_0296_amd.autotune import autotune_batch
     from paper_1209_0296_amd.serve import Server, requests_from_workload, run_one_per_launch
     from workloads import served_requests
 
-    reqs = requests_from_workload(served_requests(args.served_jobs, rate=args.served_rate))
     arena = args.served_arena_mib << 20
-    srv = Server(arena, max_jobs=4096, chunk=64)
-    # warm-up: compile and load every batched kernel once
-    srv.run(requests_from_workload(served_requests(16, rate=1e9, seed=99, sweeps=(2, 4))),
-            realtime=False)
-    outcomes, stats = srv.run(reqs, realtime=True)
-    attempts = sum(r.params.nsites * r.sweeps for r in reqs)
-    out = {"workload": f"served_ising_{len(reqs)}", "arrival_rate_per_s": args.served_rate,
-           "arena_bytes": arena, "chunk_sweeps": 64, "jobs": stats["jobs"],
-           "jobs_per_s": stats["jobs_per_s"], "p50_latency_s": stats["p50_latency_s"],
-           "p99_latency_s": stats["p99_latency_s"], "makespan_s": stats["makespan_s"],
-           "attempts_per_s": attempts / stats["makespan_s"]}
-    k = min(args.compare_jobs, len(reqs))
+    n = args.served_jobs
+    sample = requests_from_workload(served_requests(args.tune_jobs, rate=1e9, seed=7))
+    say = lambda m: print(f"# served: {m}", file=sys.stderr, flush=True)
+    say(f"autotune on {len(sample)} jobs")
+    (H, chunk), table = autotune_batch(sample, arena, chunks=(32, 64, 128, 256), log=say)
+    print(f"# batch autotuner: tile_rows {H}, chunk {chunk} "
+          f"({min(table.values()):.3f} s of {max(table.values()):.3f} s)", file=sys.stderr, flush=True)
+    srv = Server(arena, max_jobs=n, chunk=chunk, tile_rows=H)
+    closed = requests_from_workload(served_requests(n, rate=1e9))
+    attempts = sum(r.params.nsites * r.sweeps for r in closed)
+    srv.run(requests_from_workload(served_requests(64, rate=1e9, seed=99, sweeps=(2, 4))), realtime=False)
+    say(f"capacity: closed batch of {n} jobs")
+    _, cap = srv.run(closed, realtime=False)
+    rate = args.served_load * cap["jobs_per_s"]
+    stream = requests_from_workload(served_requests(n, rate=rate))
+    say(f"latency: {n} jobs at {rate:.4g} jobs/s")
+    _, live = srv.run(stream, realtime=True)
+    out = {"workload": f"served_ising_{n}", "arena_bytes": arena, "tile_rows": H, "chunk_sweeps": chunk,
+           "autotune_s": {f"{k[0]},{k[1]}": v for k, v in table.items()},
+           "capacity": {"jobs": cap["jobs"], "jobs_per_s": cap["jobs_per_s"], "makespan_s": cap["makespan_s"],
+                        "attempts_per_s": attempts / cap["makespan_s"]},
+           "offered_load": args.served_load, "arrival_rate_per_s": rate,
+           "jobs": live["jobs"], "jobs_per_s": live["jobs_per_s"], "p50_latency_s": live["p50_latency_s"],
+           "p99_latency_s": live["p99_latency_s"], "makespan_s": live["makespan_s"],
+           "attempts_per_s": attempts / cap["makespan_s"]}
+    k = min(args.compare_jobs, n)
     if k:
-        sub = reqs[:k]
+        sub = closed[:k]
+        say(f"compare: {k} jobs batched, without graphs, one per launch")
         o_b, s_b = srv.run(sub, realtime=False)
+        srv.close()
+        ng = Server(arena, max_jobs=n, chunk=chunk, tile_rows=H, flags=BATCH_NO_GRAPH)
+        ng.run(sub[: max(1, k // 8)], realtime=False)
+        o_g, s_g = ng.run(sub, realtime=False)
+        ng.close()
         o_1, s_1 = run_one_per_launch(sub, realtime=False)
-        same = all(np.array_equal(o_b[r.id].records, o_1[r.id].records) for r in sub)
+        same = all(np.array_equal(o_b[r.id].records, o_1[r.id].records) and
+                   np.array_equal(o_b[r.id].records, o_g[r.id].records) for r in sub)
         out["vs_one_per_launch"] = {"jobs": k, "batched_jobs_per_s": s_b["jobs_per_s"],
+                                    "batched_no_graph_jobs_per_s": s_g["jobs_per_s"],
                                     "one_per_launch_jobs_per_s": s_1["jobs_per_s"],
                                     "speedup": s_b["jobs_per_s"] / s_1["jobs_per_s"],
+                                    "graph_gain": s_b["jobs_per_s"] / s_g["jobs_per_s"],
                                     "identical_records": bool(same)}
-    srv.close()
+    else:
+        srv.close()
     return out
 
 
@@ -238,9 +273,11 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--served-jobs", type=int, default=4096,
                     help="jobs in the served Poisson stream (0: skip serving)")
-    ap.add_argument("--served-rate", type=float, default=1000.0, help="arrivals per second")
-    ap.add_argument("--served-arena-mib", type=int, default=512)
-    ap.add_argument("--compare-jobs", type=int, default=48,
+    ap.add_argument("--served-load", type=float, default=0.7,
+                    help="offered load of the latency run, as a fraction of the measured capacity")
+    ap.add_argument("--served-arena-mib", type=int, default=2048)
+    ap.add_argument("--tune-jobs", type=int, default=256, help="sample jobs of the batch autotuner")
+    ap.add_argument("--compare-jobs", type=int, default=512,
                     help="jobs served both batched and one run per launch (closed batch)")
     ap.add_argument("--only", default="", metavar="WORKLOAD",
                     help="time only this workload of workloads.CONFIGS and print its own JSON "
@@ -286,13 +323,21 @@ def main():
             r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)
+            per_launch_s = r["roofline"]["per_launch_us"] * 1e-6
             secondary.append({k: r[k] for k in ("workload", "attempts_per_s", "ms_per_step",
                                                  "sweep_kernels_ms_per_step", "launch")}
-                             | {"roofline_frac": r["roofline"]["frac"]})
+                             | {"roofline_frac": r["roofline"]["frac"],
+                                "per_launch_us": r["roofline"]["per_launch_us"],
+                                "algo_bytes_per_launch": r["roofline"]["algo_bytes_per_launch"],
+                                # committed counters, while the kernel sources match them
+                                "traffic": measured_traffic(key),
+                                "valu": valu_fraction(key, per_launch_s)})
     served_res = None
     if args.served_jobs > 0:
         served_res = served(args)
-        print(f"# served: {served_res['jobs_per_s']:.4g} jobs/s, p50 {served_res['p50_latency_s']:.3g} s, "
+        print(f"# served: capacity {served_res['capacity']['jobs_per_s']:.4g} jobs/s "
+              f"({served_res['capacity']['attempts_per_s']:.3g} attempts/s); at "
+              f"{served_res['offered_load']:.0%} load p50 {served_res['p50_latency_s']:.3g} s, "
               f"p99 {served_res['p99_latency_s']:.3g} s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:

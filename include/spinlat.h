@@ -88,7 +88,7 @@
 extern "C" {
 #endif
 
-#define SL_ABI_VERSION 2u
+#define SL_ABI_VERSION 3u
 
 typedef struct sl_lattice sl_lattice; /* opaque, owned by the library */
 
@@ -276,30 +276,45 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent lattices ("jobs") of uneven size, model,
- * temperature and seed advanced by shared launches (one launch per colour and
- * per class of jobs with the same model kind, dimension and words per lane).
- * Each job follows exactly the sweep of a lattice created alone with the same
- * parameters: its lattice and records are identical alone and in any mix,
- * because its random numbers depend only on its seed, sweep index and site.
+ * temperature and seed advanced by shared launches.  Each job follows exactly
+ * the sweep of a lattice created alone with the same parameters: its lattice
+ * and records are identical alone and in any mix, because its random numbers
+ * depend only on its seed, sweep index and site.
  *
  * The caller owns one device arena; the batch keeps its job table and work
  * lists at the start of it and places every job's lattice and record ring in
  * the rest.  A job is admitted only if its footprint (sl_batch_job_bytes) fits
  * in the free arena space; removing a job returns its space.
  * Batched jobs need L % 8 == 0 and a checkerboard model (SL_ISING,
- * SL_NORTH_EAST or SL_NE_COUPLED).  Jobs whose colour row splits into row
- * groups of at most 64 lanes run the whole-row kernels, the others the
- * column-window kernels (also spin-1/2 jobs with a zero threshold); coupled NE
- * jobs must fit the whole-row kernels (SL_E_UNSUPPORTED otherwise).
+ * SL_NORTH_EAST or SL_NE_COUPLED).  Each job gets a kernel class when it is
+ * admitted:
+ *   - resident: both colours fit 48 KiB; one workgroup per job runs the
+ *     call's sweeps in LDS, in one launch per call for all such jobs, on a
+ *     stream of the library's own that overlaps the other launches;
+ *   - 2D jobs whose colour row fits one wave (and, for spin-1/2 and coupled
+ *     NE, every threshold >= 1): fused sweeps (both colours in one pass, two
+ *     copies of the lattice, so twice the lattice bytes);
+ *   - 3D jobs that fit one wave likewise: half-sweeps by row groups;
+ *   - the rest: half-sweep column windows (coupled NE jobs must fit a row
+ *     class or LDS, SL_E_UNSUPPORTED otherwise).
+ * The non-resident jobs of a call share two launches per sweep (colour 0 with
+ * the fused jobs' whole sweep, colour 1), captured once per shape in a HIP
+ * graph and replayed.
  * ------------------------------------------------------------------------- */
 typedef struct sl_batch sl_batch;
+
+#define SL_BATCH_NO_GRAPH 1u    /* launch the per-sweep kernels directly, no graph replay */
+#define SL_BATCH_NO_FUSED 2u    /* 2D jobs take half-sweep walks instead of fused sweeps */
+#define SL_BATCH_NO_RESIDENT 4u /* no resident class: small jobs run with the others */
 
 typedef struct sl_batch_config {
     uint32_t abi_version;     /* SL_ABI_VERSION */
     uint32_t max_jobs;        /* size of the job table */
     uint32_t record_capacity; /* records each job holds between measurements (>= 2) */
-    int32_t tile_rows;        /* rows per strip of the batched kernels (0: default) */
+    int32_t tile_rows;        /* rows per strip of the walk and fused classes (0: default) */
     uint64_t max_workgroups;  /* size of the work list (0: default 1 << 20) */
+    uint32_t flags;           /* SL_BATCH_* (0: every class, graph replay) */
+    uint32_t reserved;        /* 0 */
 } sl_batch_config;
 
 /* Arena bytes a job with these parameters occupies (host-only, pure). */
@@ -314,13 +329,18 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
 
 /* Admit a job (params as for sl_create_lattice, record_capacity ignored) that
  * is to run `sweeps` sweeps in total.  Initialises its lattice and record r_0
- * on the stream.  SL_E_BUFFER: not enough free arena (nothing changed);
- * SL_E_STATE: job table full; SL_E_UNSUPPORTED: L % 8 != 0. */
+ * on the stream, asynchronously (SL_INIT_BUFFER: init_spins must stay valid
+ * until the stream has run the copy).  SL_E_BUFFER: not enough free arena
+ * (nothing changed); SL_E_STATE: job table full; SL_E_UNSUPPORTED: no class
+ * fits (e.g. L % 8 != 0); SL_E_OVERFLOW: t0 + sweeps would pass 2^32. */
 sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, uint32_t* job_id);
 
 /* Enqueue up to n sweeps of every job that has sweeps left and room in its
- * record ring; jobs stop individually.  Synchronises the stream once (to
- * upload the per-job counters), then enqueues asynchronously. */
+ * record ring; jobs stop individually.  Asynchronous: the per-call counters and
+ * work lists go up from double-buffered pinned staging (the host waits only if
+ * the upload of the call before the previous one has not run yet).  The first
+ * call of a shape captures its launches into a graph (SL_E_HIP if that
+ * fails). */
 sl_status sl_batch_sweep(sl_batch* b, uint64_t n);
 
 /* Per-job counters: sweeps done, sweeps left, unread records. */

@@ -11,5 +11,6 @@ from .spinlat import (  # noqa: F401
     MODE_HALF, MODE_HALF_ROWS, MODE_HALF_WINDOW, MODE_FUSED_WINDOW, MODE_RESIDENT, MODE_SIMPLE, NORTH_EAST,
     NE_COUPLED, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, RECORD_DTYPE, Lattice, Params, SpinlatError, lib,
     query_bytes, records_to_array, threshold_table, Batch, batch_config, batch_job_bytes,
-    batch_base_bytes, record_statistics, autocorrelation,
+    batch_base_bytes, record_statistics, autocorrelation, BATCH_NO_GRAPH, BATCH_NO_FUSED,
+    BATCH_NO_RESIDENT,
 )

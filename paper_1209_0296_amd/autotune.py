@@ -71,3 +71,30 @@ def autotune(p: Params, sweeps: int = 0, warmup: int = 0, device="cuda"):
         lat.close()
     best = min(table, key=table.get)
     return best, table
+
+
+def autotune_batch(requests, arena_bytes: int, tile_rows=(0, 2, 4, 8), chunks=(16, 64, 256),
+                   max_jobs: int = 4096, device="cuda", log=None):
+    """Fastest batch configuration for a sample of served requests: the strip
+    height of the walk and fused classes and the sweeps per chunk, timed as a
+    closed batch of `requests` (serve.Request) after one untimed pass of each
+    configuration.  Returns ((tile_rows, chunk), {(tile_rows, chunk): seconds}).
+    Results do not depend on the choice (every class is bit-identical to the
+    lattice run alone).  `log`, if given, is called with one line per
+    configuration as it finishes."""
+    from .serve import Server
+
+    table = {}
+    for H in tile_rows:
+        for ch in chunks:
+            srv = Server(arena_bytes, max_jobs=max_jobs, chunk=ch, tile_rows=H, device=device)
+            try:
+                srv.run(requests[: max(1, len(requests) // 8)], realtime=False)  # kernels, graphs
+                _, st = srv.run(requests, realtime=False)
+            finally:
+                srv.close()
+            table[(H, ch)] = st["makespan_s"]
+            if log:
+                log(f"tile_rows {H}, chunk {ch}: {st['makespan_s']:.3f} s")
+    best = min(table, key=table.get)
+    return best, table

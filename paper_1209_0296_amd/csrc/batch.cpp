@@ -1,10 +1,22 @@
 // batch.cpp -- host side of the batch ABI (include/spinlat.h, "Batches").
 //
-// The caller's arena holds, in order: the device job table, the per-job
-// counters {t, record slot, sweeps in this call}, the work list of the batched
-// kernels, a fold buffer for record readback, and a heap from which each
-// job's lattice (two colour arrays) and record ring are carved first-fit.
-// Admission by footprint is the heap allocation succeeding.
+// The caller's arena holds, in order: the device job table, two sets of
+// per-call upload areas (per-job counters {t, record slot, sweeps in this call,
+// current copy}, the work list in one segment per kernel family, the count and
+// offset of each segment and the list of resident jobs; calls alternate
+// between the two sets), the fold table and
+// buffer for record readback, and a heap from which each job's lattice (two
+// colour arrays, or two copies of them for fused jobs) and record ring are
+// carved first-fit.  Admission by footprint is the heap allocation succeeding.
+//
+// A call (sl_batch_sweep) uploads the counters and work lists from pinned
+// staging (double-buffered, so the host never waits for the previous call),
+// runs the resident jobs' launch on a second stream of the library's own
+// while the per-sweep launches of the other jobs run on the caller's stream,
+// and joins the two.  The per-sweep launches of the three kernel families are
+// captured once per (sweeps, grid buckets) shape into a HIP graph on one
+// stream (families one after the other: they touch disjoint jobs), and
+// replayed; the kernels read the true segment counts from device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,23 +35,48 @@ using namespace spinlat::host;
 namespace {
 
 constexpr uint64_t kDefaultMaxWG = 1ull << 20;
+constexpr size_t kGraphCache = 8;
 
 uint64_t max_wg(const sl_batch_config* c) { return c->max_workgroups ? c->max_workgroups : kDefaultMaxWG; }
 
+// One set of per-call device upload areas.
+struct UploadLayout {
+    size_t dyn, wgs, counts, res;  // offsets from the set's start
+    size_t bytes;
+};
+
+UploadLayout upload_layout(const sl_batch_config* c)
+{
+    UploadLayout u{};
+    size_t off = 0;
+    u.dyn = off;
+    off += round_up((size_t)c->max_jobs * kDynWords * sizeof(uint32_t), kAlign);
+    u.wgs = off;
+    off += round_up((size_t)max_wg(c) * sizeof(BatchWG), kAlign);
+    u.counts = off;
+    off += kAlign;
+    u.res = off;
+    off += round_up((size_t)c->max_jobs * sizeof(uint32_t), kAlign);
+    u.bytes = off;
+    return u;
+}
+
 struct BaseLayout {
-    size_t jobs, dyn, wgs, foldtab, fold, heap;
+    size_t jobs, up[2], foldtab, fold, heap;
+    UploadLayout u;
 };
 
 BaseLayout base_layout(const sl_batch_config* c)
 {
     BaseLayout b{};
+    b.u = upload_layout(c);
     size_t off = 0;
     b.jobs = off;
     off += round_up((size_t)c->max_jobs * sizeof(BatchJob), kAlign);
-    b.dyn = off;
-    off += round_up((size_t)c->max_jobs * kDynWords * sizeof(uint32_t), kAlign);
-    b.wgs = off;
-    off += round_up((size_t)max_wg(c) * sizeof(BatchWG), kAlign);
+    for (int k = 0; k < 2; ++k) {
+        b.up[k] = off;
+        off += b.u.bytes;
+    }
     b.foldtab = off;
     off += round_up((size_t)c->max_jobs * sizeof(BatchFold), kAlign);
     b.fold = off;  // every job's unread records at once
@@ -56,6 +93,8 @@ sl_status check_config(const sl_batch_config* c)
     if (c->max_jobs < 1 || c->max_jobs > (1u << 24)) return fail(SL_E_INVALID, "max_jobs out of range");
     if (c->record_capacity < 2) return fail(SL_E_INVALID, "record_capacity must be >= 2");
     if (c->tile_rows < 0) return fail(SL_E_INVALID, "tile_rows must be >= 0");
+    if (c->flags & ~(uint32_t)(SL_BATCH_NO_GRAPH | SL_BATCH_NO_FUSED | SL_BATCH_NO_RESIDENT))
+        return fail(SL_E_INVALID, "unknown batch flags 0x%x", c->flags);
     return SL_OK;
 }
 
@@ -64,18 +103,18 @@ struct JobFoot {
     size_t col_bytes, ring_bytes, total;
 };
 
-JobFoot job_foot(const sl_params* p, uint32_t cap)
+JobFoot job_foot(const sl_params* p, uint32_t cap, uint32_t copies)
 {
     JobFoot f{};
     const uint64_t nsites = p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L;
     f.nh = nsites / 2;
     f.col_bytes = round_up(f.nh, kAlign);
     f.ring_bytes = round_up((size_t)cap * kSlotWords * sizeof(int64_t), kAlign);
-    f.total = 2 * f.col_bytes + f.ring_bytes;
+    f.total = 2 * copies * f.col_bytes + f.ring_bytes;
     return f;
 }
 
-int default_rows(int dim) { return dim == 3 ? 4 : 8; }
+int default_rows(int dim, bool fused) { return fused ? 4 : dim == 3 ? 4 : 8; }
 
 struct JobHost {
     bool used = false;
@@ -84,15 +123,33 @@ struct JobHost {
     size_t off = 0;
     JobFoot foot{};
     RowGeomHost geom{};
+    uint32_t cur = 0;  // copy holding the current state (fused jobs alternate)
     uint64_t t = 0, remaining = 0, pending = 0, first_t = 0, done = 0;
     uint64_t table[kMaxLut] = {};
     size_t table_n = 0;
 };
 
+bool resident_job(const JobHost& J) { return J.geom.variant == kBvResident; }
+bool fused_job(const JobHost& J) { return J.geom.variant >= kBvFusedD4 && J.geom.variant <= kBvFusedD1; }
+
 // Kernel kind of a job's class: the model kind, with coupled NE jobs apart.
 int class_kind(const JobHost& J)
 {
     return J.params.model == SL_NE_COUPLED ? kBatchKindNeCoupled : J.kind;
+}
+
+struct GraphEntry {
+    uint64_t key;  // sweeps * 2 + upload set
+    uint32_t grid[kBatchFamilies];
+    hipGraphExec_t exec;
+};
+
+uint32_t bucket(uint64_t n)
+{
+    if (n == 0) return 0;
+    uint32_t b = 64;
+    while (b < n) b <<= 1;
+    return b;
 }
 
 }  // namespace
@@ -101,22 +158,26 @@ struct sl_batch {
     sl_batch_config cfg;
     uint8_t* arena;
     size_t arena_bytes;
-    hipStream_t stream;
+    hipStream_t stream;  // the caller's
+    hipStream_t side;    // resident jobs run here, concurrently
+    hipStream_t cap;     // graph capture only
+    hipEvent_t ev_up[2];   // per upload set: its uploads were consumed by the launches
+    hipEvent_t ev_fork, ev_join;
     BaseLayout base;
     std::vector<JobHost> jobs;
-    FreeList heap;  // free ranges of the job heap
-    BatchJob* h_job;     // pinned staging of one job-table entry
-    uint32_t* h_dyn;     // pinned [max_jobs][kDynWords]
-    BatchWG* h_wgs;      // pinned [max_wg]
+    FreeList heap;       // free ranges of the job heap
+    BatchJob* h_jobs;    // pinned [max_jobs]: one staging entry per job slot
+    uint8_t* h_up[2];    // pinned upload staging, one per upload set
     sl_record* h_stage;  // pinned [max_jobs * record_capacity]
     BatchFold* h_fold;   // pinned [max_jobs]
+    uint64_t calls;
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
 
 BatchJob* d_jobs(const sl_batch* b) { return reinterpret_cast<BatchJob*>(b->arena + b->base.jobs); }
-uint32_t* d_dyn(const sl_batch* b) { return reinterpret_cast<uint32_t*>(b->arena + b->base.dyn); }
-BatchWG* d_wgs(const sl_batch* b) { return reinterpret_cast<BatchWG*>(b->arena + b->base.wgs); }
+uint8_t* d_up(const sl_batch* b, int k) { return b->arena + b->base.up[k]; }
 
 Geom geom_of(const sl_params* p, uint64_t nh)
 {
@@ -129,12 +190,23 @@ Geom geom_of(const sl_params* p, uint64_t nh)
     return g;
 }
 
+uint8_t* col_of(const sl_batch* b, const JobHost& J, uint32_t copy, uint32_t colour)
+{
+    return b->arena + J.off + (2 * copy + colour) * J.foot.col_bytes;
+}
+
+unsigned long long* ring_of(const sl_batch* b, uint32_t j)
+{
+    const JobHost& J = b->jobs[j];
+    return reinterpret_cast<unsigned long long*>(b->arena + J.off + 2 * J.geom.copies * J.foot.col_bytes);
+}
+
 SweepArgs job_args(const sl_batch* b, uint32_t j)
 {
     const JobHost& J = b->jobs[j];
     SweepArgs a{};
-    a.col[0] = b->arena + J.off;
-    a.col[1] = b->arena + J.off + J.foot.col_bytes;
+    a.col[0] = col_of(b, J, J.cur, 0);
+    a.col[1] = col_of(b, J, J.cur, 1);
     a.g = geom_of(&J.params, J.foot.nh);
     a.key0 = (uint32_t)J.params.seed;
     a.key1 = (uint32_t)(J.params.seed >> 32);
@@ -144,12 +216,6 @@ SweepArgs job_args(const sl_batch* b, uint32_t j)
     return a;
 }
 
-unsigned long long* ring_of(const sl_batch* b, uint32_t j)
-{
-    const JobHost& J = b->jobs[j];
-    return reinterpret_cast<unsigned long long*>(b->arena + J.off + 2 * J.foot.col_bytes);
-}
-
 sl_status check_job(const sl_batch* b, uint32_t j)
 {
     if (!b) return fail(SL_E_INVALID, "NULL batch");
@@ -157,7 +223,7 @@ sl_status check_job(const sl_batch* b, uint32_t j)
     return SL_OK;
 }
 
-// Parameters of a job (record capacity from the batch) and its geometry.
+// Parameters of a job (record capacity from the batch), its class and footprint.
 sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_params* p, JobFoot* foot,
                       RowGeomHost* geom, uint64_t* table, size_t* table_n)
 {
@@ -169,19 +235,78 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     if (is_sub_lattice(p->model))
         return fail(SL_E_UNSUPPORTED, "batched jobs use the checkerboard sweep; the NE "
                                       "sub-lattice algorithm runs as a single lattice");
-    *foot = job_foot(p, cfg->record_capacity);
     *table_n = build_table(p, table);
     bool lut32 = true;
     for (size_t i = 0; i < *table_n; ++i)
         if (table[i] == 0) lut32 = false;
-    const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim);
     const bool coupled = p->model == SL_NE_COUPLED;
     const bool spin_half_table = kind_of(p) == KIND_ISING_HALF || coupled;
-    if (!batch_geom(geom_of(p, foot->nh), H, lut32 || !spin_half_table, *geom))
+    const uint64_t nh = (p->dim == 2 ? (uint64_t)p->L * p->L : (uint64_t)p->L * p->L * p->L) / 2;
+    const Geom g = geom_of(p, nh);
+    const bool fused = p->dim == 2 && !(cfg->flags & SL_BATCH_NO_FUSED);
+    const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim, fused);
+    if (!(cfg->flags & SL_BATCH_NO_RESIDENT) && batch_resident_geom(g, *geom)) {
+        // resident jobs run the direct update in LDS: any table
+    } else if (!batch_geom(g, H, lut32 || !spin_half_table, fused, *geom)) {
         return fail(SL_E_UNSUPPORTED, "L = %d does not fit the batched kernels", p->L);
-    if (coupled && geom->D == 0)
+    }
+    if (coupled && geom->variant == kBvWindow)
         return fail(SL_E_UNSUPPORTED, "batched coupled NE jobs need a colour row that fits one wave "
-                                      "and every threshold >= 1 (L = %d)", p->L);
+                                      "and every threshold >= 1 (L = %d), or a lattice that fits LDS", p->L);
+    *foot = job_foot(p, cfg->record_capacity, geom->copies);
+    return SL_OK;
+}
+
+// Per-sweep launches of one kernel family: the fused family once per sweep,
+// the others once per colour.
+hipError_t enqueue_family(sl_batch* b, int k, int f, uint64_t n, uint32_t grid, hipStream_t s)
+{
+    const UploadLayout& u = b->base.u;
+    const uint32_t* dyn = reinterpret_cast<const uint32_t*>(d_up(b, k) + u.dyn);
+    const BatchWG* wgs = reinterpret_cast<const BatchWG*>(d_up(b, k) + u.wgs);
+    const uint32_t* meta = reinterpret_cast<const uint32_t*>(d_up(b, k) + u.counts);
+    hipError_t e = hipSuccess;
+    for (uint64_t s2 = 0; s2 < n && e == hipSuccess && grid; ++s2)
+        for (uint32_t c = 0; c < (f == 2 ? 1u : 2u) && e == hipSuccess; ++c)
+            e = launch_batch_family(f, d_jobs(b), dyn, wgs, meta, grid, c, (uint32_t)s2, s);
+    return e;
+}
+
+// The per-sweep launches of the shape (n, grids) on upload set k as a graph,
+// captured on first use.
+sl_status graph_for(sl_batch* b, int k, uint64_t n, const uint32_t (&grid)[kBatchFamilies], hipGraphExec_t* out)
+{
+    const uint64_t key = n * 2 + (uint64_t)k;
+    for (const GraphEntry& g : b->graphs)
+        if (g.key == key && std::equal(grid, grid + kBatchFamilies, g.grid)) {
+            *out = g.exec;
+            return SL_OK;
+        }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "batch: begin graph capture");
+    hipError_t le = hipSuccess;
+    for (int f = 0; f < kBatchFamilies && le == hipSuccess; ++f) le = enqueue_family(b, k, f, n, grid[f], b->cap);
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : e, "batch: graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "batch: graph instantiate");
+    if (b->graphs.size() >= kGraphCache) {
+        // the oldest graph may still run: wait before destroying it
+        e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch: synchronise before graph eviction");
+        (void)hipGraphExecDestroy(b->graphs.front().exec);
+        b->graphs.erase(b->graphs.begin());
+    }
+    GraphEntry ge{key, {}, exec};
+    std::copy(grid, grid + kBatchFamilies, ge.grid);
+    b->graphs.push_back(ge);
+    *out = exec;
     return SL_OK;
 }
 
@@ -233,39 +358,38 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
     b->arena = static_cast<uint8_t*>(device_arena);
     b->arena_bytes = arena_bytes;
     b->stream = static_cast<hipStream_t>(hip_stream);
+    b->side = nullptr;
+    b->cap = nullptr;
+    b->ev_up[0] = b->ev_up[1] = nullptr;
+    b->ev_fork = b->ev_join = nullptr;
     b->base = base;
     b->jobs.resize(cfg->max_jobs);
     const size_t heap = round_up(base.heap, kAlign);
     b->heap.reset(heap, arena_bytes > heap ? (arena_bytes - heap) / kAlign * kAlign : 0);
-    b->h_job = nullptr;
-    b->h_dyn = nullptr;
-    b->h_wgs = nullptr;
+    b->h_jobs = nullptr;
+    b->h_up[0] = b->h_up[1] = nullptr;
     b->h_stage = nullptr;
     b->h_fold = nullptr;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_job), sizeof(BatchJob), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_dyn),
-                          (size_t)cfg->max_jobs * kDynWords * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_wgs), (size_t)max_wg(cfg) * sizeof(BatchWG),
-                          hipHostMallocDefault);
+    b->calls = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_jobs), (size_t)cfg->max_jobs * sizeof(BatchJob),
+                                 hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_up[k]), base.u.bytes, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_stage),
                           (size_t)cfg->max_jobs * cfg->record_capacity * sizeof(sl_record), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_fold), (size_t)cfg->max_jobs * sizeof(BatchFold),
                           hipHostMallocDefault);
+    // the library's own streams keep the default priority
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->ev_up[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         sl_batch_destroy(b);
-        return hip_fail(e, "batch: pinned staging");
-    }
-    std::memset(b->h_dyn, 0, (size_t)cfg->max_jobs * kDynWords * sizeof(uint32_t));
-    e = hipMemcpyAsync(d_dyn(b), b->h_dyn, (size_t)cfg->max_jobs * kDynWords * sizeof(uint32_t),
-                       hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        sl_batch_destroy(b);
-        return hip_fail(e, "batch: clear counters");
+        return hip_fail(e, "batch: pinned staging, streams and events");
     }
     *out = b;
     return SL_OK;
@@ -290,17 +414,22 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
     J.t = J.params.t0;
     J.first_t = J.params.t0;
     J.remaining = sweeps;
+    J.cur = 0;
     b->jobs[j] = J;
 
-    // device job-table entry
-    BatchJob* hj = b->h_job;
+    // device job-table entry, staged in this slot's own pinned entry: the
+    // slot is rewritten only after sl_batch_remove, which synchronises
+    BatchJob* hj = b->h_jobs + j;
     std::memset(hj, 0, sizeof(BatchJob));
-    hj->col[0] = b->arena + J.off;
-    hj->col[1] = b->arena + J.off + J.foot.col_bytes;
+    for (uint32_t cp = 0; cp < J.geom.copies; ++cp)
+        for (uint32_t c = 0; c < 2; ++c) hj->col[cp][c] = col_of(b, J, cp, c);
     hj->acc = ring_of(b, j);
     hj->key0 = (uint32_t)J.params.seed;
     hj->key1 = (uint32_t)(J.params.seed >> 32);
-    hj->cls = batch_class(class_kind(J), J.params.dim, J.geom.D);
+    hj->cls = batch_class(class_kind(J), J.params.dim, J.geom.variant);
+    hj->copies = J.geom.copies;
+    hj->dim = (uint32_t)J.params.dim;
+    hj->table_n = (uint32_t)J.table_n;
     std::memcpy(hj->rg_words, J.geom.bytes, sizeof(hj->rg_words));
     std::memcpy(hj->table, J.table, J.table_n * sizeof(uint64_t));
     hipError_t e = hipMemcpyAsync(d_jobs(b) + j, hj, sizeof(BatchJob), hipMemcpyHostToDevice, b->stream);
@@ -323,8 +452,8 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
         a.colour = c;
         e = launch_simple_half(a, J.kind, b->stream);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // h_job is reused by the next add
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(b->stream);
         b->heap.release(J.off, J.foot.total);
         b->jobs[j] = JobHost();
         return hip_fail(e, "batch add");
@@ -339,7 +468,7 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     if (!b) return fail(SL_E_INVALID, "NULL batch");
     if (n == 0) return SL_OK;
     const uint32_t cap = b->cfg.record_capacity;
-    uint32_t top = 0;       // one past the highest used job index
+    uint32_t top = 0;  // one past the highest used job index
     uint64_t n_eff = 0;
     std::vector<uint64_t> budget(b->jobs.size(), 0);
     for (uint32_t j = 0; j < b->jobs.size(); ++j) {
@@ -352,48 +481,103 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     }
     if (n_eff == 0) return SL_OK;
 
-    // the work list grouped by kernel variant (kind, dim, words per lane), so
-    // neighbouring workgroups of the one launch run the same code
-    uint64_t nwg = 0;
-    for (int kind : {(int)KIND_ISING_HALF, (int)KIND_ISING_ONE, (int)KIND_NE, kBatchKindNeCoupled})
-        for (int dim : {2, 3})
-            for (int D : {4, 2, 1, 0}) {
-                for (uint32_t j = 0; j < top; ++j) {
-                    const JobHost& J = b->jobs[j];
-                    if (!J.used || !budget[j] || class_kind(J) != kind || J.params.dim != dim ||
-                        J.geom.D != D)
-                        continue;
-                    const uint32_t per = J.geom.items_per_wg;
-                    const uint32_t k = (J.geom.nitems + per - 1) / per;
-                    if (nwg + k > max_wg(&b->cfg))
-                        return fail(SL_E_STATE, "work list full (%llu workgroups); raise max_workgroups",
-                                    (unsigned long long)max_wg(&b->cfg));
-                    for (uint32_t w = 0; w < k; ++w) b->h_wgs[nwg + w] = BatchWG{j, w * per};
-                    nwg += k;
+    // this call's upload set; wait until the launches that read it last (two
+    // calls ago) have been enqueued past its upload
+    const int k = (int)(b->calls & 1u);
+    hipError_t e = hipEventSynchronize(b->ev_up[k]);
+    if (e != hipSuccess) return hip_fail(e, "batch: wait for staging");
+    const UploadLayout& u = b->base.u;
+    uint8_t* hu = b->h_up[k];
+    uint32_t* h_dyn = reinterpret_cast<uint32_t*>(hu + u.dyn);
+    BatchWG* h_wgs = reinterpret_cast<BatchWG*>(hu + u.wgs);
+    uint32_t* h_counts = reinterpret_cast<uint32_t*>(hu + u.counts);
+    uint32_t* h_res = reinterpret_cast<uint32_t*>(hu + u.res);
+
+    // work list: one segment per kernel family, each grouped by class so
+    // neighbouring workgroups run the same code; resident jobs in their own list
+    uint64_t nwg = 0, nres = 0;
+    uint32_t count[kBatchFamilies] = {}, offset[kBatchFamilies] = {};
+    for (int fam = 0; fam < kBatchFamilies; ++fam) {
+        offset[fam] = (uint32_t)nwg;
+        for (uint32_t kind : {(uint32_t)KIND_ISING_HALF, (uint32_t)KIND_ISING_ONE, (uint32_t)KIND_NE,
+                              (uint32_t)kBatchKindNeCoupled})
+            for (int dim : {2, 3})
+                for (uint32_t v = 0; v < 16; ++v) {
+                    if (v == kBvResident || batch_family(v) != fam) continue;
+                    for (uint32_t j = 0; j < top; ++j) {
+                        const JobHost& J = b->jobs[j];
+                        if (!J.used || !budget[j] || (uint32_t)class_kind(J) != kind || J.params.dim != dim ||
+                            J.geom.variant != v)
+                            continue;
+                        const uint32_t per = J.geom.items_per_wg;
+                        const uint32_t kwg = (J.geom.nitems + per - 1) / per;
+                        if (nwg + kwg > max_wg(&b->cfg))
+                            return fail(SL_E_STATE, "work list full (%llu workgroups); raise max_workgroups",
+                                        (unsigned long long)max_wg(&b->cfg));
+                        for (uint32_t w = 0; w < kwg; ++w) h_wgs[nwg + w] = BatchWG{j, w * per};
+                        nwg += kwg;
+                    }
                 }
-            }
+        count[fam] = (uint32_t)nwg - offset[fam];
+    }
     for (uint32_t j = 0; j < top; ++j) {
-        uint32_t* d = b->h_dyn + kDynWords * j;
         const JobHost& J = b->jobs[j];
+        uint32_t* d = h_dyn + kDynWords * j;
         d[0] = (uint32_t)J.t;
         d[1] = (uint32_t)J.pending;
         d[2] = J.used ? (uint32_t)budget[j] : 0u;
-        d[3] = 0u;
+        d[3] = J.cur;
+        if (J.used && budget[j] && resident_job(J)) h_res[nres++] = j;
     }
-    hipError_t e = hipMemcpyAsync(d_dyn(b), b->h_dyn, (size_t)top * kDynWords * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, b->stream);
+    for (int f = 0; f < kBatchFamilies; ++f) {
+        h_counts[2 * f] = count[f];
+        h_counts[2 * f + 1] = offset[f];
+    }
+    uint8_t* du = d_up(b, k);
+    e = hipMemcpyAsync(du + u.dyn, h_dyn, (size_t)top * kDynWords * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e == hipSuccess && nwg)
+        e = hipMemcpyAsync(du + u.wgs, h_wgs, nwg * sizeof(BatchWG), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(d_wgs(b), b->h_wgs, nwg * sizeof(BatchWG), hipMemcpyHostToDevice, b->stream);
-    // the staging buffers are rewritten by the next call: wait for the copies
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    // one launch per colour for every job (the work list is grouped by
-    // variant); sweep s of the call runs sweep t + s of the jobs with more
-    // than s sweeps in this call
-    for (uint64_t s = 0; s < n_eff && e == hipSuccess; ++s)
-        for (uint32_t colour = 0; colour < 2 && e == hipSuccess; ++colour)
-            e = launch_batch_all(d_jobs(b), d_dyn(b), d_wgs(b), (uint32_t)nwg, colour, (uint32_t)s,
-                                 b->stream);
-    if (e != hipSuccess) return hip_fail(e, "batch sweep");
+        e = hipMemcpyAsync(du + u.counts, h_counts, 2 * kBatchFamilies * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess && nres)
+        e = hipMemcpyAsync(du + u.res, h_res, nres * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream);
+    // the staging of set k may be rewritten once these copies have run
+    if (e == hipSuccess) e = hipEventRecord(b->ev_up[k], b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch: upload");
+    ++b->calls;
+
+    // resident jobs: one launch on the side stream, overlapping the rest
+    if (nres) {
+        e = hipEventRecord(b->ev_fork, b->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        if (e == hipSuccess)
+            e = launch_batch_resident(d_jobs(b), reinterpret_cast<const uint32_t*>(du + u.dyn),
+                                      reinterpret_cast<const uint32_t*>(du + u.res), (uint32_t)nres, b->side);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
+        if (e != hipSuccess) return hip_fail(e, "batch: resident launch");
+    }
+    // the other jobs: n_eff sweeps of per-family launches, replayed from a graph
+    if (nwg) {
+        uint32_t grid[kBatchFamilies];
+        for (int f = 0; f < kBatchFamilies; ++f) grid[f] = bucket(count[f]);
+        if (b->cfg.flags & SL_BATCH_NO_GRAPH) {
+            for (int f = 0; f < kBatchFamilies && e == hipSuccess; ++f)
+                e = enqueue_family(b, k, f, n_eff, grid[f], b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch sweep");
+        } else {
+            hipGraphExec_t exec = nullptr;
+            sl_status gs = graph_for(b, k, n_eff, grid, &exec);
+            if (gs != SL_OK) return gs;
+            e = hipGraphLaunch(exec, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
+        }
+    }
+    if (nres) {
+        e = hipStreamWaitEvent(b->stream, b->ev_join, 0);
+        if (e != hipSuccess) return hip_fail(e, "batch: join resident launch");
+    }
     for (uint32_t j = 0; j < top; ++j) {
         JobHost& J = b->jobs[j];
         if (!J.used || !budget[j]) continue;
@@ -401,6 +585,7 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
         J.pending += budget[j];
         J.remaining -= budget[j];
         J.done += budget[j];
+        if (fused_job(J)) J.cur ^= (uint32_t)(budget[j] & 1u);
     }
     return SL_OK;
 }
@@ -450,13 +635,21 @@ sl_status sl_batch_drain(sl_batch* b, sl_record* out, uint32_t* job_of, size_t c
     for (uint32_t j = 0; j < b->jobs.size(); ++j) {
         const JobHost& J = b->jobs[j];
         if (!J.used || J.pending == 0) continue;
-        b->h_fold[ne++] = BatchFold{ring_of(b, j), total, J.first_t, (uint32_t)J.pending,
-                                    J.params.model == SL_ISING ? 1u : 0u};
         total += J.pending;
     }
     if (total == 0) return SL_OK;
     if (!out || !job_of || cap < total)
         return fail(SL_E_BUFFER, "%llu records pending, buffer holds %zu", (unsigned long long)total, cap);
+    // the fold table's staging is reused by every drain: the previous drain
+    // synchronised before returning, so its copy has run
+    total = 0;
+    for (uint32_t j = 0; j < b->jobs.size(); ++j) {
+        const JobHost& J = b->jobs[j];
+        if (!J.used || J.pending == 0) continue;
+        b->h_fold[ne++] = BatchFold{ring_of(b, j), total, J.first_t, (uint32_t)J.pending,
+                                    J.params.model == SL_ISING ? 1u : 0u};
+        total += J.pending;
+    }
     BatchFold* dtab = reinterpret_cast<BatchFold*>(b->arena + b->base.foldtab);
     int64_t* fold = reinterpret_cast<int64_t*>(b->arena + b->base.fold);
     hipError_t e = hipMemcpyAsync(dtab, b->h_fold, ne * sizeof(BatchFold), hipMemcpyHostToDevice, b->stream);
@@ -494,7 +687,9 @@ sl_status sl_batch_remove(sl_batch* b, uint32_t job_id)
 {
     sl_status st = check_job(b, job_id);
     if (st != SL_OK) return st;
-    hipError_t e = hipStreamSynchronize(b->stream);  // no queued launch may still use its memory
+    // no queued launch may still use its memory (resident launches join the
+    // caller's stream)
+    hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch remove");
     JobHost& J = b->jobs[job_id];
     b->heap.release(J.off, J.foot.total);
@@ -506,9 +701,17 @@ sl_status sl_batch_destroy(sl_batch* b)
 {
     if (!b) return fail(SL_E_INVALID, "NULL batch");
     hipError_t e = hipStreamSynchronize(b->stream);
-    if (b->h_job) (void)hipHostFree(b->h_job);
-    if (b->h_dyn) (void)hipHostFree(b->h_dyn);
-    if (b->h_wgs) (void)hipHostFree(b->h_wgs);
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    for (GraphEntry& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (int k = 0; k < 2; ++k)
+        if (b->ev_up[k]) (void)hipEventDestroy(b->ev_up[k]);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+    for (int k = 0; k < 2; ++k)
+        if (b->h_up[k]) (void)hipHostFree(b->h_up[k]);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->h_fold) (void)hipHostFree(b->h_fold);
     delete b;

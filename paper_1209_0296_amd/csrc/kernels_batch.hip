@@ -1,22 +1,42 @@
-// kernels_batch.hip -- one launch advances a half-sweep of many independent
-// lattices (jobs) of uneven size, model, temperature and seed.
+// kernels_batch.hip -- launches that advance many independent lattices (jobs)
+// of uneven size, model, temperature and seed together.
 //
 // Every job keeps its own lattice, threshold table, Philox key, sweep index
-// and record ring; the launch reads them from a device job table.  A work
-// list names the workgroups to run as (job, first item) pairs, sorted by the
-// job's kernel variant (model kind, dimension, words per lane), so a
-// workgroup only ever touches one job and its reduction goes to that job's
-// record.  Because the random numbers depend on (seed, sweep, site) only, a
-// job's lattice and records are the same alone and in any mix.
+// and record ring; the launches read them from a device job table.  Because
+// the random numbers depend on (seed, sweep, site) only, a job's lattice and
+// records are the same alone and in any mix.
 //
-// Per-job counters {t, record slot, sweeps in this call} live in a small
-// device array that the host uploads once per call; the launches of the
-// call's s-th sweep take s as an argument, so a job runs sweep t + s into
-// record slot + s while s is below its count, and nothing runs between the
-// sweeps to move the counters.
-#include "row_device.hpp"
-#include "stream_device.hpp"
+// Job classes (chosen by the host when a job is admitted):
+//   - resident: the lattice (both colours) fits 48 KiB of LDS.  One launch per
+//     call runs every resident job's sweeps of the call, one workgroup per job,
+//     the whole chunk of sweeps in LDS (k_batch_resident).
+//   - fused (2D): both colours of a sweep in the colour-0 launch, strips of
+//     whole rows with the colour-0 halo rows recomputed, reading one copy of
+//     the job's lattice and writing the other.
+//   - rows (3D): one colour per launch, each colour row updated by its own
+//     row group (no walk).
+//   - walk / window: one colour per launch, whole-row walks down strips, or
+//     64-lane column windows for rows that fit no wave.
+// The non-resident classes form three kernel families, each with its own
+// kernel so that its register budget is its own: half (walks and windows) and
+// rows launch once per colour, fused once per sweep (all colour work of the
+// fused jobs).  A work list names the workgroups as (job, first item) pairs in
+// one segment per family, sorted by class, so a workgroup touches one job and
+// its reduction goes to that job's record.  The number of valid entries and
+// the offset of each segment are read from device memory, so a grid rounded
+// up to a bucket size can be captured once in a graph and replayed for any
+// mix whose counts fit the bucket.
+//
+// Per-job counters {t, record slot, sweeps in this call, current copy} live in
+// a device array the host uploads once per call; the launches of the call's
+// s-th sweep take s as an argument, so a job runs sweep t + s into record slot
+// + s while s is below its count, and nothing runs between the sweeps to move
+// the counters.
 #include "batch_internal.h"
+#include "row_device.hpp"
+#include "rows_device.hpp"
+#include "simple_device.hpp"
+#include "stream_device.hpp"
 
 namespace spinlat {
 
@@ -24,59 +44,94 @@ using namespace rowk;
 
 namespace {
 
-template <int KIND, int DIM, int D>
-__device__ __forceinline__ void batch_half_body(const BatchJob* __restrict__ jobs, const uint32_t* __restrict__ dyn,
-                                                const BatchWG w, uint32_t colour, uint32_t step,
-                                                RowLuts& lut, uint32_t (&xch)[2][16][2])
+__device__ __forceinline__ SweepArgs job_sweep_args(const BatchJob& J, const uint32_t* dj, uint32_t colour,
+                                                    uint32_t step)
 {
-    const uint32_t* dj = dyn + kDynWords * w.job;
-    if (step >= dj[2]) return;  // whole workgroup: this job has no sweep left in this call
-    const BatchJob& J = jobs[w.job];
-    uint64_t thr_up, thr_down;
-    build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
-    __syncthreads();
-
     SweepArgs a{};
-    a.col[0] = J.col[0];
-    a.col[1] = J.col[1];
+    const bool second = J.copies == 2 && ((dj[3] + step) & 1u);
+    a.col[0] = second ? J.col[1][0] : J.col[0][0];
+    a.col[1] = second ? J.col[1][1] : J.col[0][1];
     a.key0 = J.key0;
     a.key1 = J.key1;
     a.t = dj[0] + step;
     a.colour = colour;
+    return a;
+}
+
+template <int KIND, int DIM, int D>
+__device__ __forceinline__ void batch_walk_body(const BatchJob& J, const uint32_t* dj, const BatchWG w, uint32_t colour,
+                                                uint32_t step, RowLuts& lut, uint32_t (&xch)[2][16][2])
+{
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
+    __syncthreads();
+    const SweepArgs a = job_sweep_args(J, dj, colour, step);
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
     const uint32_t slot_in_wave = ln.lane / rg.R;
-    const uint32_t item = slot_in_wave < rg.slots
-                              ? w.item_base + ln.wave * rg.slots + slot_in_wave
-                              : 0xFFFFFFFFu;
+    const uint32_t item = slot_in_wave < rg.slots ? w.item_base + ln.wave * rg.slots + slot_in_wave : 0xFFFFFFFFu;
     half_item<KIND, DIM, D, false>(a, rg, item, ln, lut, xch, thr_up, thr_down, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
     block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
 }
 
-// Jobs whose colour row does not fit one wave (or whose spin-1/2 table has a
-// zero threshold): 64-lane column windows with edge loads (any L % 8 == 0).
+template <int KIND, int DIM, int D>
+__device__ __forceinline__ void batch_rows_body(const BatchJob& J, const uint32_t* dj, const BatchWG w, uint32_t colour,
+                                                uint32_t step, RowLuts& lut)
+{
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
+    __syncthreads();
+    const SweepArgs a = job_sweep_args(J, dj, colour, step);
+    const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
+    Obs o = {0, 0, 0, 0, 0};
+    const Lanes ln = lanes_of(rg, false);
+    const RowsAt at = rows_at(rg, w.item_base + ln.wave, ln.lane / rg.R);
+    if (at.ok) {
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        RowsIn<DIM, D> in;
+        rows_load<DIM, D>(in, a, rg, at, ln);
+        rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+    }
+    int32_t bond, mag, acc, unfl;
+    finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
+    block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
+}
+
+// 2D jobs with two copies: the whole sweep, reading copy cur and writing the
+// other.
+template <int KIND, int D>
+__device__ __forceinline__ void batch_fused_body(const BatchJob& J, const uint32_t* dj, const BatchWG w, uint32_t step,
+                                                 RowLuts& lut, uint32_t (&xch)[2][16][4])
+{
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, 2>(lut, J.table, thr_up, thr_down);
+    __syncthreads();
+    const SweepArgs a = job_sweep_args(J, dj, 0u, step);  // the current copy
+    const bool second = (dj[3] + step) & 1u;
+    uint8_t* const N0 = second ? J.col[0][0] : J.col[1][0];  // the other copy
+    uint8_t* const N1 = second ? J.col[0][1] : J.col[1][1];
+    const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
+    Obs o = {0, 0, 0, 0, 0};
+    const Lanes ln = lanes_of(rg, false);
+    const uint32_t slot_in_wave = ln.lane / rg.R;
+    const uint32_t item = slot_in_wave < rg.slots ? w.item_base + ln.wave * rg.slots + slot_in_wave : 0xFFFFFFFFu;
+    fused_item<KIND, D, false, 0>(a, rg, item, ln, lut, xch, thr_up, thr_down, a.col[0], a.col[1], N0, N1, o);
+    int32_t bond, mag, acc, unfl;
+    finish_obs<KIND, 2>(o, bond, mag, acc, unfl);
+    block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
+}
+
 template <int KIND, int DIM>
-__device__ __forceinline__ void batch_window_body(const BatchJob* __restrict__ jobs,
-                                                  const uint32_t* __restrict__ dyn, const BatchWG w,
+__device__ __forceinline__ void batch_window_body(const BatchJob& J, const uint32_t* dj, const BatchWG w,
                                                   uint32_t colour, uint32_t step, streamk::Luts& lut)
 {
-    const uint32_t* dj = dyn + kDynWords * w.job;
-    if (step >= dj[2]) return;  // whole workgroup: no sweep left for this job
-    const BatchJob& J = jobs[w.job];
     uint64_t thr_up, thr_down;
     streamk::build_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
     __syncthreads();
-
-    SweepArgs a{};
-    a.col[0] = J.col[0];
-    a.col[1] = J.col[1];
-    a.key0 = J.key0;
-    a.key1 = J.key1;
-    a.t = dj[0] + step;
-    a.colour = colour;
+    const SweepArgs a = job_sweep_args(J, dj, colour, step);
     const streamk::StreamGeom sg = *reinterpret_cast<const streamk::StreamGeom*>(J.rg_words);
     streamk::Obs o = {0, 0, 0, 0};
     const uint32_t lane = threadIdx.x & 63u;
@@ -85,58 +140,99 @@ __device__ __forceinline__ void batch_window_body(const BatchJob* __restrict__ j
     block_accumulate(o.bond, o.mag, o.acc, o.unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
 }
 
-// Every job of a half-sweep in one launch: each workgroup runs the variant of
-// its job (the work list is sorted by variant, so neighbouring workgroups run
-// the same code).
 union BatchLds {
     RowLuts row;
     streamk::Luts win;
 };
 
-template <int KIND, int DIM>
-__device__ __forceinline__ void dispatch_d(uint32_t d, const BatchJob* jobs, const uint32_t* dyn, const BatchWG w,
-                                           uint32_t colour, uint32_t step, BatchLds& lds,
-                                           uint32_t (&xch)[2][16][2])
-{
-    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, step, lds.row, xch);
-    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, step, lds.row, xch);
-    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, step, lds.row, xch);
-    else batch_window_body<KIND, DIM>(jobs, dyn, w, colour, step, lds.win);
-}
+// Kernel families: each launch runs one family's variants only, so its
+// register budget is that of its own bodies.
+constexpr int kFamHalf = 0, kFamRows = 1, kFamFused = 2;
 
-// Coupled NE jobs run only the whole-row bodies (the host admits no other).
-template <int KIND, int DIM>
-__device__ __forceinline__ void dispatch_rows(uint32_t d, const BatchJob* jobs, const uint32_t* dyn,
-                                              const BatchWG w, uint32_t colour, uint32_t step, BatchLds& lds,
-                                              uint32_t (&xch)[2][16][2])
+template <int FAM, int KIND, int DIM>
+__device__ __forceinline__ void dispatch(uint32_t v, const BatchJob& J, const uint32_t* dj, const BatchWG w,
+                                         uint32_t colour, uint32_t step, BatchLds& lds, uint32_t (&xch)[2][16][4])
 {
-    if (d == 0) batch_half_body<KIND, DIM, 4>(jobs, dyn, w, colour, step, lds.row, xch);
-    else if (d == 1) batch_half_body<KIND, DIM, 2>(jobs, dyn, w, colour, step, lds.row, xch);
-    else if (d == 2) batch_half_body<KIND, DIM, 1>(jobs, dyn, w, colour, step, lds.row, xch);
+    if constexpr (FAM == kFamHalf) {
+        uint32_t(&xch2)[2][16][2] = *reinterpret_cast<uint32_t(*)[2][16][2]>(&xch);
+        if (v == kBvWalkD4) batch_walk_body<KIND, DIM, 4>(J, dj, w, colour, step, lds.row, xch2);
+        else if (v == kBvWalkD2) batch_walk_body<KIND, DIM, 2>(J, dj, w, colour, step, lds.row, xch2);
+        else if (v == kBvWalkD1) batch_walk_body<KIND, DIM, 1>(J, dj, w, colour, step, lds.row, xch2);
+        else if constexpr (KIND != KIND_NE_COUPLED) {
+            if (v == kBvWindow) batch_window_body<KIND, DIM>(J, dj, w, colour, step, lds.win);
+        }
+    } else if constexpr (FAM == kFamRows) {
+        if (v == kBvRowsD4) batch_rows_body<KIND, DIM, 4>(J, dj, w, colour, step, lds.row);
+        else if (v == kBvRowsD2) batch_rows_body<KIND, DIM, 2>(J, dj, w, colour, step, lds.row);
+        else if (v == kBvRowsD1) batch_rows_body<KIND, DIM, 1>(J, dj, w, colour, step, lds.row);
+    } else if constexpr (DIM == 2) {
+        if (v == kBvFusedD2) batch_fused_body<KIND, 2>(J, dj, w, step, lds.row, xch);
+        else if (v == kBvFusedD1) batch_fused_body<KIND, 1>(J, dj, w, step, lds.row, xch);
+    }
 }
 
 static_assert(kBatchKindNeCoupled == KIND_NE_COUPLED, "batch class kind of coupled NE jobs");
 
-__global__ void __launch_bounds__(256) k_batch_all(const BatchJob* __restrict__ jobs,
-                                                   const uint32_t* __restrict__ dyn,
-                                                   const BatchWG* __restrict__ wgs, uint32_t colour,
-                                                   uint32_t step)
+// One family's launch: meta = {count, offset} of the family's work-list
+// segment (valid entries; the grid may be larger: a bucket size).
+template <int FAM>
+__global__ void __launch_bounds__(256) k_batch_family(const BatchJob* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ dyn,
+                                                      const BatchWG* __restrict__ wgs,
+                                                      const uint32_t* __restrict__ meta, uint32_t colour, uint32_t step)
 {
     __shared__ BatchLds lds;
-    __shared__ uint32_t xch[2][16][2];
-    const BatchWG w = wgs[blockIdx.x];
-    const uint32_t cls = jobs[w.job].cls;
-    const uint32_t kind = cls >> 3, dim3d = (cls >> 2) & 1u, d = cls & 3u;
+    __shared__ uint32_t xch[2][16][4];
+    if (blockIdx.x >= meta[2 * FAM]) return;  // whole workgroup
+    const BatchWG w = wgs[meta[2 * FAM + 1] + blockIdx.x];
+    const uint32_t* dj = dyn + kDynWords * w.job;
+    if (step >= dj[2]) return;  // whole workgroup: no sweep left for this job in this call
+    const BatchJob& J = jobs[w.job];
+    const uint32_t kind = J.cls >> 5, dim3d = (J.cls >> 4) & 1u, v = J.cls & 15u;
     if (kind == KIND_ISING_HALF) {
-        if (dim3d) dispatch_d<KIND_ISING_HALF, 3>(d, jobs, dyn, w, colour, step, lds, xch);
-        else dispatch_d<KIND_ISING_HALF, 2>(d, jobs, dyn, w, colour, step, lds, xch);
+        if (dim3d) dispatch<FAM, KIND_ISING_HALF, 3>(v, J, dj, w, colour, step, lds, xch);
+        else dispatch<FAM, KIND_ISING_HALF, 2>(v, J, dj, w, colour, step, lds, xch);
     } else if (kind == KIND_ISING_ONE) {
-        if (dim3d) dispatch_d<KIND_ISING_ONE, 3>(d, jobs, dyn, w, colour, step, lds, xch);
-        else dispatch_d<KIND_ISING_ONE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
+        if (dim3d) dispatch<FAM, KIND_ISING_ONE, 3>(v, J, dj, w, colour, step, lds, xch);
+        else dispatch<FAM, KIND_ISING_ONE, 2>(v, J, dj, w, colour, step, lds, xch);
     } else if (kind == KIND_NE) {
-        dispatch_d<KIND_NE, 2>(d, jobs, dyn, w, colour, step, lds, xch);
+        dispatch<FAM, KIND_NE, 2>(v, J, dj, w, colour, step, lds, xch);
     } else {
-        dispatch_rows<KIND_NE_COUPLED, 2>(d, jobs, dyn, w, colour, step, lds, xch);
+        dispatch<FAM, KIND_NE_COUPLED, 2>(v, J, dj, w, colour, step, lds, xch);
+    }
+}
+
+// One workgroup per resident job: all of the job's sweeps of this call in LDS.
+__global__ void __launch_bounds__(simplek::kResidentBlock) k_batch_resident(const BatchJob* __restrict__ jobs,
+                                                                           const uint32_t* __restrict__ dyn,
+                                                                           const uint32_t* __restrict__ list)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    __shared__ uint64_t lut[kMaxLut];
+    const uint32_t j = list[blockIdx.x];
+    const uint32_t* dj = dyn + kDynWords * j;
+    const uint32_t n = dj[2];
+    if (n == 0) return;
+    const BatchJob& J = jobs[j];
+    SweepArgs a = job_sweep_args(J, dj, 0u, 0u);
+    const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
+    a.g.L = rg.L;
+    a.g.Lh = rg.Lh;
+    a.g.dim = J.dim;
+    a.g.rows = J.dim == 2 ? rg.L : rg.L * rg.L;
+    a.g.nh = (uint64_t)a.g.rows * rg.Lh;  // the resident geometry keeps only L and Lh
+    a.lut = J.table;
+    a.lut_n = (int32_t)J.table_n;
+    a.acc = J.acc + (uint64_t)dj[1] * kSlotWords;
+    const uint32_t kind = J.cls >> 5;
+    if (kind == KIND_ISING_HALF) {
+        if (J.dim == 3) simplek::resident_run<KIND_ISING_HALF, 3>(a, n, sm, lut);
+        else simplek::resident_run<KIND_ISING_HALF, 2>(a, n, sm, lut);
+    } else if (kind == KIND_ISING_ONE) {
+        if (J.dim == 3) simplek::resident_run<KIND_ISING_ONE, 3>(a, n, sm, lut);
+        else simplek::resident_run<KIND_ISING_ONE, 2>(a, n, sm, lut);
+    } else {
+        simplek::resident_run<KIND_NE, 2>(a, n, sm, lut);  // J = 0 or coupled (lut_n > 2)
     }
 }
 
@@ -165,30 +261,66 @@ __global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict_
 
 }  // namespace
 
-bool batch_geom(const Geom& g, int H, bool lut32_ok, RowGeomHost& out)
+bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHost& out)
 {
-    // widest D whose row group fits one wave (the whole-row batched kernel
-    // has no cross-wave exchange) ...
-    for (int D : {4, 2, 1}) {
-        if (!lut32_ok) break;
+    out = RowGeomHost{};
+    static_assert(sizeof(RowGeom) <= sizeof(out.bytes), "RowGeom storage");
+    static_assert(sizeof(streamk::StreamGeom) <= sizeof(out.bytes), "StreamGeom storage");
+    if (lut32_ok) {
         RowGeom rg;
-        if (!make_row_geom(g, H, D, false, rg)) continue;
-        if (rg.R > 64) continue;
-        static_assert(sizeof(RowGeom) <= sizeof(out.bytes), "RowGeom storage");
-        __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
-        out.D = D;
-        out.nitems = rg.nitems;
-        out.items_per_wg = 4 * rg.slots;
-        return true;
+        if (g.dim == 3) {
+            // row groups without a walk, widest D whose row fits one wave
+            for (int D : {4, 2, 1}) {
+                if (!make_rows_geom(g, D, 4, rg)) continue;
+                __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
+                out.variant = D == 4 ? kBvRowsD4 : D == 2 ? kBvRowsD2 : kBvRowsD1;
+                out.nitems = rg.nitems;
+                out.items_per_wg = 4;
+                return true;
+            }
+        } else if (allow_fused) {
+            // two or one words per lane (colour rows up to L = 1024)
+            for (int D : {2, 1}) {
+                if (!make_row_geom(g, H, D, true, rg) || rg.R > 64) continue;
+                __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
+                out.variant = D == 2 ? kBvFusedD2 : kBvFusedD1;
+                out.nitems = rg.nitems;
+                out.items_per_wg = 4 * rg.slots;
+                out.copies = 2;
+                return true;
+            }
+        }
+        // whole-row walks within one wave
+        for (int D : {4, 2, 1}) {
+            if (!make_row_geom(g, H, D, false, rg) || rg.R > 64) continue;
+            __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
+            out.variant = D == 4 ? kBvWalkD4 : D == 2 ? kBvWalkD2 : kBvWalkD1;
+            out.nitems = rg.nitems;
+            out.items_per_wg = 4 * rg.slots;
+            return true;
+        }
     }
-    // ... else column windows (D = 0)
+    // column windows
     if (g.Lh % 4) return false;
     const streamk::StreamGeom sg = streamk::make_geom(g, H, false);
-    static_assert(sizeof(streamk::StreamGeom) <= sizeof(out.bytes), "StreamGeom storage");
     __builtin_memcpy(out.bytes, &sg, sizeof(sg));
-    out.D = 0;
+    out.variant = kBvWindow;
     out.nitems = sg.nitems;
     out.items_per_wg = 4 * sg.G;
+    return true;
+}
+
+bool batch_resident_geom(const Geom& g, RowGeomHost& out)
+{
+    out = RowGeomHost{};
+    if (2 * g.nh > (uint64_t)kResidentLds) return false;
+    RowGeom rg{};
+    rg.L = g.L;
+    rg.Lh = g.Lh;
+    __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
+    out.variant = kBvResident;
+    out.nitems = 1;
+    out.items_per_wg = 1;
     return true;
 }
 
@@ -199,11 +331,26 @@ hipError_t launch_batch_fold(const BatchFold* tab, uint32_t nentries, int64_t* o
     return hipGetLastError();
 }
 
-hipError_t launch_batch_all(const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs, uint32_t nwg,
-                            uint32_t colour, uint32_t step, hipStream_t s)
+hipError_t launch_batch_family(int family, const BatchJob* jobs, const uint32_t* dyn, const BatchWG* wgs,
+                               const uint32_t* meta, uint32_t grid, uint32_t colour, uint32_t step, hipStream_t s)
 {
-    if (nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_all, dim3(nwg), dim3(256), 0, s, jobs, dyn, wgs, colour, step);
+    if (grid == 0) return hipSuccess;
+    if (family == kFamHalf)
+        hipLaunchKernelGGL(k_batch_family<kFamHalf>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour, step);
+    else if (family == kFamRows)
+        hipLaunchKernelGGL(k_batch_family<kFamRows>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour, step);
+    else
+        hipLaunchKernelGGL(k_batch_family<kFamFused>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour,
+                           step);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_resident(const BatchJob* jobs, const uint32_t* dyn, const uint32_t* list, uint32_t njobs,
+                                 hipStream_t s)
+{
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_resident, dim3(njobs), dim3(simplek::kResidentBlock), kResidentLds, s, jobs, dyn,
+                       list);
     return hipGetLastError();
 }
 

@@ -490,8 +490,8 @@ __device__ __forceinline__ void half_item(const SweepArgs& a, const RowGeom& rg,
         const uint32_t zp = item / rg.nstrips;
         const uint32_t L = rg.L;
         const uint32_t c = a.colour;
-        const uint8_t* O = a.col[c ^ 1u];
-        uint8_t* A = a.col[c];
+        const uint8_t* O = colour_array(a, c ^ 1u);
+        uint8_t* A = colour_array(a, c);
         const uint64_t rowb = rg.Lh;
         const uint64_t cb = 4ull * D * ln.pos;
         const uint64_t plane = (uint64_t)zp * L;
@@ -622,6 +622,71 @@ __device__ __forceinline__ void fused_step_p(int i, FusedState<KIND, D>& st, con
     else
         fused_step<KIND, D, XW, 1, DO_C1, STORE0, PREF>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
                                                          thr_up, thr_down, o);
+}
+
+// Fused sweep (both colours) of strip `item` (rows item*H .. item*H + H - 1)
+// for this lane's row group, reading copy (S0, S1) and writing (D0, D1).
+// HT > 0: the strip height is the compile-time HT (even, dividing L), so every
+// row's parity is known (y0 = item * HT is even) and the rows run in parity
+// pairs with no per-row branch.  HT = 0: runtime strip height rg.H (any
+// H >= 1, ragged last strip).
+template <int KIND, int D, bool XW, int HT>
+__device__ __forceinline__ void fused_item(const SweepArgs& a, const RowGeom& rg, uint32_t item, const Lanes& ln,
+                                           const RowLuts& lut, uint32_t (&xch)[2][16][4], uint64_t thr_up,
+                                           uint64_t thr_down, const uint8_t* S0, const uint8_t* S1, uint8_t* D0,
+                                           uint8_t* D1, Obs& o)
+{
+    if (item < rg.nitems) {
+        const uint32_t L = rg.L;
+        const uint64_t rowb = rg.Lh;
+        const uint64_t cb = 4ull * D * ln.pos;
+        const int H = HT > 0 ? HT : (int)rg.H;
+        const int y0 = (int)(item * (uint32_t)H);
+        const int y1 = min(y0 + H, (int)L);
+        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+        FusedState<KIND, D> st;
+        st.c1a = ldv<D>(S1, (uint64_t)wrap1(y0 - 2, L) * rowb + cb);
+        st.c1b = ldv<D>(S1, (uint64_t)wrap1(y0 - 1, L) * rowb + cb);
+        st.c1d = ldv<D>(S1, (uint64_t)wrap1(y0, L) * rowb + cb);
+        st.q1a = prepv<KIND, D>(st.c1a);
+        st.q1b = prepv<KIND, D>(st.c1b);
+        st.q1d = prepv<KIND, D>(st.c1d);
+        st.own0 = ldv<D>(S0, (uint64_t)wrap1(y0 - 1, L) * rowb + cb);
+#pragma unroll
+        for (int d = 0; d < D; ++d) st.q0a.w[d] = st.q0b.w[d] = 0u;
+        uint32_t buf = 0;
+        // halo row y0-1 (colour 0 only, not stored), first row y0 (colour 0
+        // only), rows y0+1 .. y1-1, halo row y1 (colour 1 of row y1-1 only)
+        if constexpr (HT > 0) {
+            // y0 is even, so row y0 + k has parity k & 1
+            fused_step<KIND, D, XW, 1, false, false, true>(y0 - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a,
+                                                           ks, lut, thr_up, thr_down, o);
+            fused_step<KIND, D, XW, 0, false, true, true>(y0, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks,
+                                                          lut, thr_up, thr_down, o);
+            // rows y0 + 1 .. y0 + HT - 1 in pairs of parity (1, 0), then row y0 + HT - 1
+#pragma nounroll
+            for (int k = 1; k + 1 < HT; k += 2) {
+                fused_step<KIND, D, XW, 1, true, true, true>(y0 + k, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks,
+                                                             lut, thr_up, thr_down, o);
+                fused_step<KIND, D, XW, 0, true, true, true>(y0 + k + 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a,
+                                                             ks, lut, thr_up, thr_down, o);
+            }
+            fused_step<KIND, D, XW, 1, true, true, true>(y0 + HT - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks,
+                                                         lut, thr_up, thr_down, o);
+            fused_step<KIND, D, XW, 0, true, false, false>(y0 + HT, st, rg, ln, S0, S1, D0, D1, xch, buf, a,
+                                                           ks, lut, thr_up, thr_down, o);
+        } else {
+            fused_step_p<KIND, D, XW, false, false, true>(y0 - 1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks,
+                                                          lut, thr_up, thr_down, o);
+            fused_step_p<KIND, D, XW, false, true, true>(y0, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                         thr_up, thr_down, o);
+            for (int i = y0 + 1; i < y1; ++i)
+                fused_step_p<KIND, D, XW, true, true, true>(i, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                            thr_up, thr_down, o);
+            fused_step_p<KIND, D, XW, true, false, false>(y1, st, rg, ln, S0, S1, D0, D1, xch, buf, a, ks, lut,
+                                                          thr_up, thr_down, o);
+        }
+    }
 }
 
 // Host: whole-row geometry for strip height H and D words per lane.

@@ -1,0 +1,121 @@
+// rows_device.hpp -- device code of the half-sweep by independent row groups
+// (SL_MODE_HALF_ROWS), shared by the single-lattice kernel (kernels_rows.hip)
+// and the batched kernel (kernels_batch.hip).
+//
+// One colour is updated per launch (Alg. I steps 5-7: the kernel end separates
+// the colours).  Every row group of R lanes owns one colour row outright: it
+// loads its own D words per lane and the other colour's rows y-1, y, y+1 (and,
+// in 3D, the rows of planes z-1 and z+1) with one vector load each, updates,
+// stores, and is done.  There is no walk along y, so no prologue whose latency
+// a short walk cannot hide; instead many short waves keep every SIMD busy
+// while others wait on memory.  The neighbour rows a wave loads overlap those
+// of the adjacent waves and come from the caches.
+//
+// A row set is 64 / R row groups' worth of rows, all of one row parity: row set
+// w of plane z holds rows y = q + 2 (j * slots + slot) with q = w & 1,
+// j = w >> 1, so the side the same-row neighbour sits on (p = (y + z + c) & 1)
+// is uniform across a wave.  Each wave takes one row set.  (Measured and
+// dropped: waves that take several row sets and load the next while updating
+// the current one were slower at every depth.)
+#pragma once
+#include "row_device.hpp"
+
+namespace spinlat {
+namespace rowk {
+
+// The neighbour words one row group needs for one row, raw.
+template <int DIM, int D>
+struct RowsIn {
+    Vec<D> own, o0, om, op, zm, zp;
+};
+
+// Row set `it` of the launch (wave-uniform) and this lane's row in it.
+struct RowsAt {
+    uint32_t z, y;
+    bool ok;  // this lane's row group has a row here
+};
+
+__device__ __forceinline__ RowsAt rows_at(const RowGeom& rg, uint32_t it, uint32_t slot)
+{
+    RowsAt r;
+    r.z = it / rg.nstrips;
+    const uint32_t rem = it - r.z * rg.nstrips;
+    r.y = (rem & 1u) + 2u * ((rem >> 1) * rg.slots + slot);
+    r.ok = it < rg.nitems && slot < rg.slots && r.y < rg.L;
+    return r;
+}
+
+template <int DIM, int D>
+__device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg, const RowsAt& at,
+                                          const Lanes& ln)
+{
+    if (!at.ok) return;
+    const uint32_t L = rg.L, z = at.z, y = at.y;
+    const uint32_t c = a.colour;
+    const uint8_t* O = colour_array(a, c ^ 1u);
+    const uint64_t rowb = rg.Lh;
+    const uint64_t cb = 4ull * D * ln.pos;
+    const uint64_t plane = (uint64_t)z * L;
+    const uint64_t row = plane + y;
+    in.own = ldv<D>(colour_array(a, c), row * rowb + cb);
+    in.o0 = ldv<D>(O, row * rowb + cb);
+    in.om = ldv<D>(O, (plane + (y == 0 ? L - 1 : y - 1)) * rowb + cb);
+    in.op = ldv<D>(O, (plane + (y + 1 == L ? 0 : y + 1)) * rowb + cb);
+    if constexpr (DIM == 3) {
+        in.zm = ldv<D>(O, ((uint64_t)(z == 0 ? L - 1 : z - 1) * L + y) * rowb + cb);
+        in.zp = ldv<D>(O, ((uint64_t)(z + 1 == L ? 0 : z + 1) * L + y) * rowb + cb);
+    }
+}
+
+template <int KIND, int DIM, int D, int P>
+__device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
+                                            const RowsAt& at, const Lanes& ln, const PhiloxKey& ks,
+                                            const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o)
+{
+    const uint64_t row = (uint64_t)at.z * rg.L + at.y;
+    const uint64_t cb = 4ull * D * ln.pos;
+    const Vec<D> q0 = prepv<KIND, D>(in.o0);
+    const uint32_t x = shift_in<false, P>(q0.w[D - 1], q0.w[0], ln, 0u);
+    uint32_t side[D];
+    side_words<D, P>(q0, x, side);
+    const Vec<D> qm = prepv<KIND, D>(in.om);
+    const Vec<D> qp = prepv<KIND, D>(in.op);
+    Vec<D> qzm, qzp;
+    if constexpr (DIM == 3) {
+        qzm = prepv<KIND, D>(in.zm);
+        qzp = prepv<KIND, D>(in.zp);
+    }
+    const uint32_t g0 = (uint32_t)(row * rg.ncols + (uint64_t)D * ln.pos);
+    const Vec<D> nw = row_update<KIND, DIM, D, P>(in.own, q0, side, qm, qp, &qzm, &qzp, g0, a.colour, a.t, ks, lut,
+                                                  thr_up, thr_down, true, o);
+    stv<D>(colour_array(a, a.colour), row * rg.Lh + cb, nw);
+}
+
+template <int KIND, int DIM, int D>
+__device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
+                                          const RowsAt& at, const Lanes& ln, const PhiloxKey& ks, const RowLuts& lut,
+                                          uint64_t thr_up, uint64_t thr_down, Obs& o)
+{
+    if (!at.ok) return;
+    // the row parity is uniform across the wave: every row of a row set has
+    // the parity of rem & 1
+    if (((at.y + at.z + a.colour) & 1u) == 0)
+        rows_update<KIND, DIM, D, 0>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+    else
+        rows_update<KIND, DIM, D, 1>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+}
+
+// Row groups of one wave at most; the row sets per plane go to nstrips, the
+// launch's to nitems, the threads per block (waves >= 1 waves of 64, at most
+// 16) to block.
+inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg)
+{
+    if (waves < 1 || waves > 16 || !make_row_geom(g, 1, D, false, rg) || rg.R > 64) return false;
+    rg.nstrips = 2 * cdiv(g.L, 2 * rg.slots);
+    rg.nitems = rg.nstrips * rg.nplanes;
+    rg.block = 64u * (uint32_t)waves;
+    return true;
+}
+
+}  // namespace rowk
+}  // namespace spinlat

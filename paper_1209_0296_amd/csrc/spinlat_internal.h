@@ -37,6 +37,14 @@ struct SweepArgs {
     int32_t tile_words;
 };
 
+// Colour array c of a sweep's lattice, by select rather than array index: the
+// batched kernels build SweepArgs in registers, where a runtime index would
+// put the array in scratch memory.
+__device__ __forceinline__ uint8_t* colour_array(const SweepArgs& a, uint32_t c)
+{
+    return c ? a.col[1] : a.col[0];
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, hipStream_t s);
 hipError_t launch_init(const SweepArgs& a, int kind, int init_mode, uint32_t bern_thr_lo,
                        uint32_t bern_thr_hi, hipStream_t s);

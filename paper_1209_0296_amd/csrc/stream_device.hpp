@@ -329,8 +329,8 @@ __device__ __forceinline__ void stream_half_item(const SweepArgs& a, const Strea
             if (li == 63) colE = (J + 64) % sg.ncols;
         }
         const uint32_t c = a.colour;
-        const uint8_t* O = a.col[c ^ 1u];
-        uint8_t* A = a.col[c];
+        const uint8_t* O = colour_array(a, c ^ 1u);
+        uint8_t* A = colour_array(a, c);
         const uint32_t L = sg.L;
         const uint64_t plane = (uint64_t)zp * L;
         const uint64_t rowb = sg.Lh;  // bytes per colour row

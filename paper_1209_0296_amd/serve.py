@@ -59,10 +59,10 @@ class Server:
     """Admit by footprint, sweep resident jobs in chunks, retire as they finish."""
 
     def __init__(self, arena_bytes: int, max_jobs: int = 1024, chunk: int = 64,
-                 tile_rows: int = 0, device="cuda"):
+                 tile_rows: int = 0, device="cuda", flags: int = 0):
         self.chunk = chunk
         self.batch = Batch(arena_bytes, max_jobs=max_jobs, record_capacity=chunk + 1,
-                           tile_rows=tile_rows, device=device)
+                           tile_rows=tile_rows, device=device, flags=flags)
 
     def run(self, requests, realtime: bool = True):
         """Serve `requests` (sorted by arrival).  With realtime=False every

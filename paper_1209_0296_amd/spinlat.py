@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspinlat.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
+BATCH_NO_GRAPH, BATCH_NO_FUSED, BATCH_NO_RESIDENT = 1, 2, 4
 ISING, NORTH_EAST, NE_SUBLATTICE, NE_SUBLATTICE_BALANCED, NE_COUPLED = 0, 1, 2, 3, 4
 INIT_COLD, INIT_RANDOM, INIT_BUFFER = 0, 1, 2
 MODE_AUTO, MODE_SIMPLE, MODE_HALF, MODE_FUSED = 0, 1, 2, 3
@@ -62,7 +63,8 @@ class CRecord(ctypes.Structure):
 class CBatchConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("max_jobs", ctypes.c_uint32),
                 ("record_capacity", ctypes.c_uint32), ("tile_rows", ctypes.c_int32),
-                ("max_workgroups", ctypes.c_uint64)]
+                ("max_workgroups", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class CStats(ctypes.Structure):
@@ -358,8 +360,8 @@ def records_to_array(records: np.ndarray) -> np.ndarray:
 # Batches of independent lattices sharing launches
 
 def batch_config(max_jobs: int = 1024, record_capacity: int = 256, tile_rows: int = 0,
-                 max_workgroups: int = 0) -> CBatchConfig:
-    return CBatchConfig(ABI_VERSION, max_jobs, record_capacity, tile_rows, max_workgroups)
+                 max_workgroups: int = 0, flags: int = 0) -> CBatchConfig:
+    return CBatchConfig(ABI_VERSION, max_jobs, record_capacity, tile_rows, max_workgroups, flags, 0)
 
 
 def batch_job_bytes(p: Params, cfg: CBatchConfig) -> int:
@@ -384,13 +386,14 @@ class Batch:
     """
 
     def __init__(self, arena_bytes: int, max_jobs: int = 1024, record_capacity: int = 256,
-                 tile_rows: int = 0, device="cuda", stream=None, max_workgroups: int = 0):
+                 tile_rows: int = 0, device="cuda", stream=None, max_workgroups: int = 0,
+                 flags: int = 0):
         import torch
 
         self._torch = torch
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.cfg = batch_config(max_jobs, record_capacity, tile_rows, max_workgroups)
+        self.cfg = batch_config(max_jobs, record_capacity, tile_rows, max_workgroups, flags)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         self._init_refs = {}
         h = ctypes.c_void_p()
@@ -416,6 +419,8 @@ class Batch:
             return None
         _check(st)
         self.params[jid.value] = p
+        if ptr:
+            self._init_refs[jid.value] = t  # the copy runs on the stream later
         return jid.value
 
     def sweep(self, n: int) -> None:
@@ -466,6 +471,7 @@ class Batch:
     def remove(self, job: int) -> None:
         _check(lib().sl_batch_remove(self._h, job))
         self.params.pop(job, None)
+        self._init_refs.pop(job, None)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

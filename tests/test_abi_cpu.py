@@ -128,6 +128,28 @@ def test_status_strings():
         assert S.lib().sl_status_str(code).decode() == name
 
 
+def test_batch_flags_checked():
+    n = ctypes.c_size_t()
+    cfg = S.batch_config(max_jobs=4, record_capacity=8, flags=8)
+    assert S.lib().sl_batch_base_bytes(ctypes.byref(cfg), ctypes.byref(n)) == 1
+    cfg = S.batch_config(max_jobs=4, record_capacity=8, flags=S.BATCH_NO_GRAPH | S.BATCH_NO_FUSED)
+    assert S.lib().sl_batch_base_bytes(ctypes.byref(cfg), ctypes.byref(n)) == 0
+
+
+def test_batch_footprints_by_class():
+    """Fused 2D jobs hold two copies of the lattice; resident and half-sweep
+    jobs one."""
+    cfg = S.batch_config(max_jobs=4, record_capacity=8)
+    half = S.batch_config(max_jobs=4, record_capacity=8, flags=S.BATCH_NO_FUSED)
+    ring = 8 * 16 * 16 * 8
+    colour = lambda q: (q.nsites // 2 + 255) // 256 * 256  # one colour array, 256-byte aligned
+    p = S.Params(L=512)  # 2D row class: fused by default
+    assert S.batch_job_bytes(p, cfg) == 4 * colour(p) + ring
+    assert S.batch_job_bytes(p, half) == 2 * colour(p) + ring
+    for q in (S.Params(L=64), S.Params(dim=3, L=64), S.Params(L=936)):  # resident, rows, window
+        assert S.batch_job_bytes(q, cfg) == 2 * colour(q) + ring
+
+
 def test_batch_shapes():
     cfg = S.batch_config(max_jobs=4, record_capacity=8)
     with pytest.raises(S.SpinlatError) as e:
@@ -155,9 +177,10 @@ def test_sub_lattice_jobs_not_batched():
     n = ctypes.c_size_t()
     cp = S.Params(model=S.NE_SUBLATTICE, L=64).c_struct()
     assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == 2
-    # coupled NE jobs: whole-row classes only (rows within one wave, thresholds >= 1)
+    # coupled NE jobs: the resident class (any table) or the whole-row classes
+    # (rows within one wave, thresholds >= 1), never the column windows
     for kw, code in ((dict(L=64), 0), (dict(L=512), 0), (dict(L=2056), 2), (dict(L=936), 2),
-                     (dict(L=64, T=1e-300), 2)):
+                     (dict(L=64, T=1e-300), 0), (dict(L=512, T=1e-300), 2)):
         cp = S.Params(model=S.NE_COUPLED, J=1.0, h=0.1, **{"T": 2.0, **kw}).c_struct()
         assert S.lib().sl_batch_job_bytes(ctypes.byref(cp), ctypes.byref(cfg), ctypes.byref(n)) == code, kw
 

@@ -35,9 +35,17 @@ def _check_job(batch, jid, sp, recs, nsweeps):
     np.testing.assert_array_equal(batch.spins(jid), o_s)
 
 
-def test_mixed_batch_matches_each_job_alone():
+FLAGS = [0, S.BATCH_NO_GRAPH, S.BATCH_NO_FUSED | S.BATCH_NO_RESIDENT,
+         S.BATCH_NO_GRAPH | S.BATCH_NO_FUSED | S.BATCH_NO_RESIDENT]
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+def test_mixed_batch_matches_each_job_alone(flags):
+    """Every class (resident, fused, row groups, walks, windows), with and
+    without graph replay."""
+    print(f"case mixed batch flags={flags}", flush=True)
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=64)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=64, flags=flags)
     ids = [b.add(p, sweeps=12) for p in jobs]
     assert all(i is not None for i in ids)
     recs = {i: [S.records_to_array(b.measure(i))] for i in ids}
@@ -133,7 +141,7 @@ def test_batch_equals_standalone_lattice():
 
     p = S.Params(L=256, T=2.269, seed=41, record_capacity=32)
     g_s, g_r = run_gpu(p, 20)
-    b = S.Batch(arena_bytes=16 << 20, max_jobs=4, record_capacity=32)
+    b = S.Batch(arena_bytes=48 << 20, max_jobs=4, record_capacity=32)
     j = b.add(p, sweeps=20)
     r = [S.records_to_array(b.measure(j))]
     b.sweep(20)
@@ -143,10 +151,13 @@ def test_batch_equals_standalone_lattice():
     b.close()
 
 
-def test_drain_collects_every_job():
-    """sl_batch_drain (one fold launch, one copy) gives each job's records."""
+@pytest.mark.parametrize("flags", FLAGS)
+def test_drain_collects_every_job(flags):
+    """sl_batch_drain (one fold launch, one copy) gives each job's records; the
+    chunks of 7 sweeps flip the fused jobs' current copy every call."""
+    print(f"case drain flags={flags}", flush=True)
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=8)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=8, flags=flags)
     ids = [b.add(p, sweeps=10 + k) for k, p in enumerate(jobs)]
     recs = {i: [] for i in ids}
     while True:
@@ -159,3 +170,53 @@ def test_drain_collects_every_job():
     for i, p in zip(ids, jobs):
         _check_job(b, i, p, recs[i], b.status(i)[0])
     b.close()
+
+
+def test_graph_replay_across_changing_mixes():
+    """Jobs join and leave between calls of the same shape (the captured graph
+    is replayed with other work lists); lattices are read mid-run, between
+    calls of odd length, from the fused jobs' alternating copies."""
+    b = S.Batch(arena_bytes=128 << 20, max_jobs=32, record_capacity=16)
+    live = {}
+    specs = [S.Params(L=L, T=2.0 + 0.01 * k, seed=200 + k, two_s=1 + (k % 2), dim=2 if k % 3 else 3)
+             for k, L in enumerate([64, 128, 256, 512, 48, 96, 32, 160, 64, 128, 256, 80])]
+    specs = [S.Params(**{**p.__dict__, "L": min(p.L, 64) if p.dim == 3 else p.L}) for p in specs]
+    rounds = 0
+    pending = list(range(len(specs)))
+    while pending or live:
+        while pending and len(live) < 6:
+            k = pending.pop(0)
+            j = b.add(specs[k], sweeps=9 + 4 * (k % 3))
+            live[j] = (k, [S.records_to_array(b.measure(j))])
+        b.sweep(5)
+        rounds += 1
+        for j, (k, recs) in list(live.items()):
+            recs.append(S.records_to_array(b.measure(j)))
+            done, remaining, _ = b.status(j)
+            if rounds % 2 == 1 or remaining == 0:
+                o_s, o_r = run_oracle(specs[k], done)
+                np.testing.assert_array_equal(np.vstack(recs), o_r)
+                np.testing.assert_array_equal(b.spins(j), o_s)
+            if remaining == 0:
+                b.remove(j)
+                del live[j]
+    b.close()
+
+
+def test_job_table_full_is_not_an_error():
+    """With max_jobs below what the arena holds, add() returns None when the
+    table is full, and the server queues the request until a slot frees."""
+    from paper_1209_0296_amd.serve import Request, Server
+
+    b = S.Batch(arena_bytes=64 << 20, max_jobs=2, record_capacity=8)
+    assert b.add(S.Params(L=64, seed=1), 4) is not None
+    assert b.add(S.Params(L=64, seed=2), 4) is not None
+    assert b.add(S.Params(L=64, seed=3), 4) is None
+    b.close()
+    reqs = [Request(i, 0.0, S.Params(L=64 if i % 2 else 128, T=2.2, seed=300 + i), 10 + i) for i in range(9)]
+    srv = Server(64 << 20, max_jobs=3, chunk=4)
+    outcomes, stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats["jobs"] == len(reqs)
+    for r in reqs:
+        np.testing.assert_array_equal(outcomes[r.id].records, run_oracle(r.params, r.sweeps)[1])
