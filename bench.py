@@ -92,9 +92,25 @@ def _lattice(S, cfg, T=None, record_capacity=4096):
     return p, S.Lattice(p)
 
 
-def time_workload(S, torch, name, cfg, steps, warmup, T=None):
-    """Warm up, then time `steps` sweeps plus the drain of their records."""
-    p, lat = _lattice(S, cfg, T=T, record_capacity=max(steps, warmup) + 2)
+def prewarm(lat, seconds, chunk):
+    """Untimed sweeps of the lattice until `seconds` of wall time have passed.
+    The GPU clock ramps up only after some tens of ms under load, which a few
+    warm-up sweeps of a lattice that takes 20-50 us per sweep do not cover.
+    Returns the number of sweeps run."""
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        lat.sweep(chunk)
+        lat.measure()
+        n += chunk
+    return n
+
+
+def time_workload(S, torch, name, cfg, steps, warmup, T=None, prewarm_s=0.0):
+    """Pre-warm, warm up, then time `steps` sweeps plus the drain of their
+    records."""
+    p, lat = _lattice(S, cfg, T=T, record_capacity=max(steps, warmup, 64) + 2)
+    pre = prewarm(lat, prewarm_s, 64) if prewarm_s > 0 else 0
     lat.sweep(warmup)
     lat.measure()
     stream = lat.stream
@@ -130,7 +146,7 @@ def time_workload(S, torch, name, cfg, steps, warmup, T=None):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "per_launch_us": per_launch_s * 1e6, "algo_bytes_per_launch": bytes_per_launch},
-        "nsites": p.nsites, "steps": steps,
+        "nsites": p.nsites, "steps": steps, "prewarm_sweeps": pre,
     }
 
 
@@ -212,12 +228,15 @@ def served(args):
 
     arena = args.served_arena_mib << 20
     n = args.served_jobs
-    sample = requests_from_workload(served_requests(args.tune_jobs, rate=1e9, seed=7))
     say = lambda m: print(f"# served: {m}", file=sys.stderr, flush=True)
-    say(f"autotune on {len(sample)} jobs")
-    (H, chunk), table = autotune_batch(sample, arena, chunks=(32, 64, 128, 256), log=say)
-    print(f"# batch autotuner: tile_rows {H}, chunk {chunk} "
-          f"({min(table.values()):.3f} s of {max(table.values()):.3f} s)", file=sys.stderr, flush=True)
+    if args.tune_jobs > 0:
+        sample = requests_from_workload(served_requests(args.tune_jobs, rate=1e9, seed=7))
+        say(f"autotune on {len(sample)} jobs")
+        (H, chunk), table = autotune_batch(sample, arena, chunks=(32, 64, 128, 256), log=say)
+        say(f"batch autotuner: tile_rows {H}, chunk {chunk} "
+            f"({min(table.values()):.3f} s of {max(table.values()):.3f} s)")
+    else:
+        H, chunk, table = 0, args.served_chunk, {}
     srv = Server(arena, max_jobs=n, chunk=chunk, tile_rows=H)
     closed = requests_from_workload(served_requests(n, rate=1e9))
     attempts = sum(r.params.nsites * r.sweeps for r in closed)
@@ -226,8 +245,10 @@ def served(args):
     _, cap = srv.run(closed, realtime=False)
     rate = args.served_load * cap["jobs_per_s"]
     stream = requests_from_workload(served_requests(n, rate=rate))
-    say(f"latency: {n} jobs at {rate:.4g} jobs/s")
-    _, live = srv.run(stream, realtime=True)
+    live = {k: None for k in ("jobs", "jobs_per_s", "p50_latency_s", "p99_latency_s", "makespan_s")}
+    if args.served_latency:
+        say(f"latency: {n} jobs at {rate:.4g} jobs/s")
+        _, live = srv.run(stream, realtime=True)
     out = {"workload": f"served_ising_{n}", "arena_bytes": arena, "tile_rows": H, "chunk_sweeps": chunk,
            "autotune_s": {f"{k[0]},{k[1]}": v for k, v in table.items()},
            "capacity": {"jobs": cap["jobs"], "jobs_per_s": cap["jobs_per_s"], "makespan_s": cap["makespan_s"],
@@ -267,6 +288,9 @@ def main():
     # the GPU clock takes ~20 ms of load to ramp up: 50 warm-up sweeps of the
     # 2D lattice measured 46.3 us per sweep, 500 measured 43.0 and 2000 42.7
     ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--prewarm-s", type=float, default=0.2,
+                    help="untimed sweeps for this many seconds before the warm-up steps of each "
+                         "workload, so that the GPU clock has ramped up (0: none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 2D L=64 and L=32768, 3D L=256 and NE L=4096 lines")
@@ -276,7 +300,12 @@ def main():
     ap.add_argument("--served-load", type=float, default=0.7,
                     help="offered load of the latency run, as a fraction of the measured capacity")
     ap.add_argument("--served-arena-mib", type=int, default=2048)
-    ap.add_argument("--tune-jobs", type=int, default=256, help="sample jobs of the batch autotuner")
+    ap.add_argument("--tune-jobs", type=int, default=256,
+                    help="sample jobs of the batch autotuner (0: no tuning, default strip "
+                         "heights and --served-chunk)")
+    ap.add_argument("--served-chunk", type=int, default=256, help="sweeps per chunk without tuning")
+    ap.add_argument("--served-latency", type=int, default=1,
+                    help="0: skip the run at the offered load (capacity and comparison only)")
     ap.add_argument("--compare-jobs", type=int, default=512,
                     help="jobs served both batched and one run per launch (closed batch)")
     ap.add_argument("--only", default="", metavar="WORKLOAD",
@@ -308,19 +337,22 @@ def main():
     from workloads import CONFIGS
 
     if args.only:
-        r = time_workload(S, torch, args.only, CONFIGS[args.only], args.steps, args.warmup)
+        r = time_workload(S, torch, args.only, CONFIGS[args.only], args.steps, args.warmup,
+                          prewarm_s=args.prewarm_s)
         print(json.dumps(r), flush=True)
         return
 
     cfg2 = CONFIGS["ising2d_L8192"]
-    main_res = time_workload(S, torch, "ising2d_L8192_T2.269", cfg2, args.steps, args.warmup)
+    main_res = time_workload(S, torch, "ising2d_L8192_T2.269", cfg2, args.steps, args.warmup,
+                             prewarm_s=args.prewarm_s)
     print(f"# 2D L=8192: {main_res['attempts_per_s']:.4g} attempts/s, "
           f"{main_res['ms_per_step']:.4f} ms/sweep", file=sys.stderr, flush=True)
     secondary = []
     if not args.no_secondary:
         for key in ("ising2d_L64", "ising2d_L32768", "ising3d_L256_s12", "ising3d_L256_s1",
                     "ne2d_L4096", "ne2d_sub_L4096", "ne2d_subbal_L4096", "ne2d_coupled_L4096"):
-            r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup)
+            r = time_workload(S, torch, key, CONFIGS[key], args.steps, args.warmup,
+                              prewarm_s=args.prewarm_s)
             print(f"# {key}: {r['attempts_per_s']:.4g} attempts/s, {r['ms_per_step']:.4f} ms/sweep",
                   file=sys.stderr, flush=True)
             per_launch_s = r["roofline"]["per_launch_us"] * 1e-6
@@ -337,8 +369,8 @@ def main():
         served_res = served(args)
         print(f"# served: capacity {served_res['capacity']['jobs_per_s']:.4g} jobs/s "
               f"({served_res['capacity']['attempts_per_s']:.3g} attempts/s); at "
-              f"{served_res['offered_load']:.0%} load p50 {served_res['p50_latency_s']:.3g} s, "
-              f"p99 {served_res['p99_latency_s']:.3g} s", file=sys.stderr, flush=True)
+              f"{served_res['offered_load']:.0%} load p50 {served_res['p50_latency_s']} s, "
+              f"p99 {served_res['p99_latency_s']} s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         threads = baseline_threads()
@@ -353,6 +385,8 @@ def main():
         "value": main_res["attempts_per_s"],
         "unit": "flip attempts/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "prewarm": {"seconds": args.prewarm_s, "sweeps": main_res["prewarm_sweeps"],
+                    "note": "untimed sweeps before the warm-up steps, until the GPU clock has ramped up"},
         "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",

@@ -69,8 +69,7 @@ __device__ __forceinline__ void batch_walk_body(const BatchJob& J, const uint32_
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
-    const uint32_t slot_in_wave = ln.lane / rg.R;
-    const uint32_t item = slot_in_wave < rg.slots ? w.item_base + ln.wave * rg.slots + slot_in_wave : 0xFFFFFFFFu;
+    const uint32_t item = ln.slot < rg.slots ? w.item_base + ln.wave * rg.slots + ln.slot : 0xFFFFFFFFu;
     half_item<KIND, DIM, D, false>(a, rg, item, ln, lut, xch, thr_up, thr_down, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
@@ -81,20 +80,11 @@ template <int KIND, int DIM, int D>
 __device__ __forceinline__ void batch_rows_body(const BatchJob& J, const uint32_t* dj, const BatchWG w, uint32_t colour,
                                                 uint32_t step, RowLuts& lut)
 {
-    uint64_t thr_up, thr_down;
-    build_row_luts<KIND, DIM>(lut, J.table, thr_up, thr_down);
-    __syncthreads();
     const SweepArgs a = job_sweep_args(J, dj, colour, step);
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
-    const RowsAt at = rows_at(rg, w.item_base + ln.wave, ln.lane / rg.R);
-    if (at.ok) {
-        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-        RowsIn<DIM, D> in;
-        rows_load<DIM, D>(in, a, rg, at, ln);
-        rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
-    }
+    rows_run<KIND, DIM, D>(a, rg, w.item_base + ln.wave * rg.K, ln, J.table, lut, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
     block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
@@ -116,8 +106,7 @@ __device__ __forceinline__ void batch_fused_body(const BatchJob& J, const uint32
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
-    const uint32_t slot_in_wave = ln.lane / rg.R;
-    const uint32_t item = slot_in_wave < rg.slots ? w.item_base + ln.wave * rg.slots + slot_in_wave : 0xFFFFFFFFu;
+    const uint32_t item = ln.slot < rg.slots ? w.item_base + ln.wave * rg.slots + ln.slot : 0xFFFFFFFFu;
     fused_item<KIND, D, false, 0>(a, rg, item, ln, lut, xch, thr_up, thr_down, a.col[0], a.col[1], N0, N1, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, 2>(o, bond, mag, acc, unfl);
@@ -275,7 +264,7 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHo
                 __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
                 out.variant = D == 4 ? kBvRowsD4 : D == 2 ? kBvRowsD2 : kBvRowsD1;
                 out.nitems = rg.nitems;
-                out.items_per_wg = 4;
+                out.items_per_wg = 4 * rg.K;
                 return true;
             }
         } else if (allow_fused) {

@@ -10,27 +10,16 @@ using namespace rowk;
 namespace {
 
 // rg.nstrips holds the row sets (waves' worth of rows) of one plane, both
-// parities; rg.nitems those of the launch.  One row set per wave; the block
+// parities; rg.nitems those of the launch.  rg.K row sets per wave; the block
 // has blockDim.x / 64 waves.
 template <int KIND, int DIM, int D>
 __global__ void __launch_bounds__(1024) k_rows_half(SweepArgs a, RowGeom rg)
 {
     __shared__ RowLuts lut;
-    uint64_t thr_up, thr_down;
-    build_row_luts<KIND, DIM>(lut, a.lut, thr_up, thr_down);
-    __syncthreads();
-
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
-    const uint32_t slot = ln.lane / rg.R;
-    const uint32_t it = remap_block() * (blockDim.x >> 6) + ln.wave;
-    const RowsAt at = rows_at(rg, it, slot);
-    if (at.ok) {
-        const PhiloxKey ks = philox_schedule(a.key0, a.key1);
-        RowsIn<DIM, D> in;
-        rows_load<DIM, D>(in, a, rg, at, ln);
-        rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
-    }
+    const uint32_t it0 = (remap_block() * (blockDim.x >> 6) + ln.wave) * rg.K;
+    rows_run<KIND, DIM, D>(a, rg, it0, ln, a.lut, lut, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
     block_accumulate(bond, mag, acc, unfl, a.acc);
@@ -39,7 +28,7 @@ __global__ void __launch_bounds__(1024) k_rows_half(SweepArgs a, RowGeom rg)
 template <int KIND, int DIM>
 void launch_rows_k(const SweepArgs& a, const RowGeom& rg, hipStream_t s)
 {
-    const dim3 grid(cdiv(rg.nitems, rg.block / 64)), block(rg.block);
+    const dim3 grid(cdiv(rg.nitems, rg.block / 64 * rg.K)), block(rg.block);
     if (rg.D == 4) hipLaunchKernelGGL((k_rows_half<KIND, DIM, 4>), grid, block, 0, s, a, rg);
     else if (rg.D == 2) hipLaunchKernelGGL((k_rows_half<KIND, DIM, 2>), grid, block, 0, s, a, rg);
     else hipLaunchKernelGGL((k_rows_half<KIND, DIM, 1>), grid, block, 0, s, a, rg);

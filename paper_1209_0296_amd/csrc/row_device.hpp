@@ -46,6 +46,8 @@ struct RowGeom {
     uint32_t nw;      // waves per row group (R > 64)
     uint32_t nplanes, H, nstrips, nitems;
     uint32_t block;   // threads per block
+    uint32_t rdiv;    // ceil(2^16 / R): lane / R == (lane * rdiv) >> 16 for every lane < 64
+    uint32_t K;       // row sets per wave (row-group kernels)
 };
 
 __host__ __device__ inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
@@ -108,7 +110,7 @@ __device__ __forceinline__ void stv(uint8_t* base, uint64_t off, const Vec<D>& v
 // of the lane to its left, for p = 1 the first word of the lane to its right
 // (periodic within the row group).
 struct Lanes {
-    uint32_t lane, wave, pos, src_l, src_r;
+    uint32_t lane, wave, slot, pos, src_l, src_r;  // wave is wave-uniform
 };
 
 template <bool XW, int P>
@@ -156,7 +158,11 @@ __device__ __forceinline__ void build_row_luts(RowLuts& lut, const uint64_t* tab
                                                uint64_t& thr_down)
 {
     constexpr int z = 2 * DIM;
-    for (int t = threadIdx.x; t < 6 * (2 * z + 1); t += blockDim.x) {
+    // entries each kind reads: spin-1/2 tables 2 (z + 1), spin-1 6 (2z + 1), NE none
+    constexpr int n = (KIND == KIND_ISING_HALF || KIND == KIND_NE_COUPLED) ? 2 * (z + 1)
+                      : KIND == KIND_ISING_ONE                             ? 6 * (2 * z + 1)
+                                                                           : 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
         if (KIND == KIND_ISING_HALF || KIND == KIND_NE_COUPLED) {
             if (t < 2 * (z + 1)) {
                 // entry nd + sneg*(z+1): nd neighbours at -1, sneg = (s == -1)
@@ -396,12 +402,15 @@ __device__ __forceinline__ Lanes lanes_of(const RowGeom& rg, bool xw)
 {
     Lanes ln;
     ln.lane = threadIdx.x & 63u;
-    ln.wave = threadIdx.x >> 6;
+    // uniform across the wave: what depends only on it stays on the scalar unit
+    ln.wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (xw) {
+        ln.slot = 0;
         ln.pos = threadIdx.x;
         ln.src_l = ln.src_r = 0;
     } else {
-        const uint32_t slot = ln.lane / rg.R;
+        const uint32_t slot = __umul24(ln.lane, rg.rdiv) >> 16;  // ln.lane / rg.R
+        ln.slot = slot;
         ln.pos = ln.lane - slot * rg.R;
         const uint32_t base = slot * rg.R;
         ln.src_l = base + (ln.pos == 0 ? rg.R - 1 : ln.pos - 1);
@@ -415,9 +424,8 @@ __device__ __forceinline__ uint32_t row_item(const RowGeom& rg, bool xw, const L
 {
     const uint32_t b = remap_block();
     if (xw) return b;
-    const uint32_t slot = ln.lane / rg.R;
-    if (slot >= rg.slots) return 0xFFFFFFFFu;
-    return (b * (blockDim.x >> 6) + ln.wave) * rg.slots + slot;
+    if (ln.slot >= rg.slots) return 0xFFFFFFFFu;
+    return (b * (blockDim.x >> 6) + ln.wave) * rg.slots + ln.slot;
 }
 
 // ---- HALF -----------------------------------------------------------------
@@ -700,6 +708,8 @@ inline bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg)
     if (rg.ncols % (uint32_t)D) return false;
     rg.D = (uint32_t)D;
     rg.R = rg.ncols / rg.D;
+    if (rg.R == 0) return false;
+    rg.rdiv = (65536u + rg.R - 1u) / rg.R;
     if (rg.R <= 64) {
         rg.slots = 64 / rg.R;
         rg.nw = 1;
@@ -713,6 +723,7 @@ inline bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg)
     if (fused && g.dim != 2) return false;
     rg.nplanes = g.dim == 3 ? g.L : 1;
     rg.H = (uint32_t)H;
+    rg.K = 1;
     rg.nstrips = cdiv(g.L, rg.H);
     rg.nitems = rg.nstrips * rg.nplanes;
     return true;

@@ -14,9 +14,12 @@
 // A row set is 64 / R row groups' worth of rows, all of one row parity: row set
 // w of plane z holds rows y = q + 2 (j * slots + slot) with q = w & 1,
 // j = w >> 1, so the side the same-row neighbour sits on (p = (y + z + c) & 1)
-// is uniform across a wave.  Each wave takes one row set.  (Measured and
-// dropped: waves that take several row sets and load the next while updating
-// the current one were slower at every depth.)
+// is uniform across a wave.  A wave takes K = 4 / D consecutive row sets one
+// after the other, so every lane updates four words per launch whatever the
+// row width.  (Measured and dropped: waves that load the next row set while
+// updating the current one were slower at every depth, and so was issuing the
+// first set's loads before the threshold table is built: the loaded words
+// live across the table build and the registers cut the waves per SIMD.)
 #pragma once
 #include "row_device.hpp"
 
@@ -114,7 +117,28 @@ inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg)
     rg.nstrips = 2 * cdiv(g.L, 2 * rg.slots);
     rg.nitems = rg.nstrips * rg.nplanes;
     rg.block = 64u * (uint32_t)waves;
+    rg.K = 4u / rg.D;
     return true;
+}
+
+// Row sets it0 .. it0 + K - 1 of one wave (it0 wave-uniform, K = 4 / D).  Every thread of
+// the block calls this: the table build inside ends in a workgroup barrier.
+template <int KIND, int DIM, int D>
+__device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, uint32_t it0, const Lanes& ln,
+                                         const uint64_t* table, RowLuts& lut, Obs& o)
+{
+    uint64_t thr_up, thr_down;
+    build_row_luts<KIND, DIM>(lut, table, thr_up, thr_down);
+    lds_barrier();
+    const PhiloxKey ks = philox_schedule(a.key0, a.key1);
+    constexpr uint32_t K = 4 / D;  // rg.K
+#pragma nounroll
+    for (uint32_t k = 0; k < K; ++k) {
+        const RowsAt at = rows_at(rg, it0 + k, ln.slot);
+        RowsIn<DIM, D> in;
+        rows_load<DIM, D>(in, a, rg, at, ln);
+        rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+    }
 }
 
 }  // namespace rowk

@@ -50,20 +50,41 @@ __device__ __forceinline__ int move_ne(int byte, int north, int east, uint32_t u
     return ((uint64_t)u < thr) ? ((n ^ 1) | 2) : byte;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores in
+// flight stay in flight across it (a full barrier also waits for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sum of v over the 64 lanes of a wave whose lanes are all active, as a
+// wave-uniform value: DPP butterflies inside each row of 16 lanes (quad
+// permutes [1,0,3,2] and [2,3,0,1], then the half-row and row mirrors leave
+// every lane holding its row's sum), then the four row sums read out.
+__device__ __forceinline__ int32_t wave_sum(int32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
+
 // Sum four per-thread int32 partials over the workgroup and add them to one
 // of the kSub sub-slots of the record (integer atomics: the result does not
-// depend on the order).  blockDim.x must be a multiple of 64, <= 1024.
+// depend on the order).  blockDim.x must be a multiple of 64, <= 1024, and
+// every thread of the block calls this.
 __device__ __forceinline__ void block_accumulate(int32_t v0, int32_t v1, int32_t v2, int32_t v3,
                                                  unsigned long long* acc)
 {
     __shared__ int32_t part[16][kQ];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v0 += __shfl_xor(v0, off, 64);
-        v1 += __shfl_xor(v1, off, 64);
-        v2 += __shfl_xor(v2, off, 64);
-        v3 += __shfl_xor(v3, off, 64);
-    }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    v3 = wave_sum(v3);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     if (lane == 0) {
@@ -72,7 +93,7 @@ __device__ __forceinline__ void block_accumulate(int32_t v0, int32_t v1, int32_t
         part[wave][2] = v2;
         part[wave][3] = v3;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x < kQ) {
         const int nw = blockDim.x >> 6;
         int64_t sum = 0;
