@@ -297,9 +297,12 @@ sl_status sl_record_observables(const sl_params* params, const sl_record* record
  *   - 3D jobs that fit one wave likewise: half-sweeps by row groups;
  *   - the rest: half-sweep column windows (coupled NE jobs must fit a row
  *     class or LDS, SL_E_UNSUPPORTED otherwise).
- * The non-resident jobs of a call share two launches per sweep (colour 0 with
- * the fused jobs' whole sweep, colour 1), captured once per shape in a HIP
- * graph and replayed.
+ * The non-resident jobs of a call share launches by kernel family: one per
+ * sweep for the fused jobs, one per colour for the row groups and for the
+ * other half-sweep classes.  They are captured once per shape into HIP graphs
+ * and replayed; the row-group family runs on another stream of the library's
+ * own, beside the other families.  Every stream the library uses is joined
+ * back into the caller's stream within each sl_batch_sweep call.
  * ------------------------------------------------------------------------- */
 typedef struct sl_batch sl_batch;
 

@@ -68,7 +68,9 @@ def build(verbose: bool = True, incremental: bool = False) -> str:
             if rc != 0:
                 raise subprocess.CalledProcessError(rc, cmd)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs,
+           # roctx ranges around the sweep calls (a no-op without a profiler)
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

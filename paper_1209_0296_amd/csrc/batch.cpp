@@ -14,9 +14,11 @@
 // runs the resident jobs' launch on a second stream of the library's own
 // while the per-sweep launches of the other jobs run on the caller's stream,
 // and joins the two.  The per-sweep launches of the three kernel families are
-// captured once per (sweeps, grid buckets) shape into a HIP graph on one
-// stream (families one after the other: they touch disjoint jobs), and
-// replayed; the kernels read the true segment counts from device memory.
+// captured once per (sweeps, grid buckets) shape into HIP graphs, each on one
+// stream, and replayed; the kernels read the true segment counts from device
+// memory.  The row-group family runs on a third stream of the library's,
+// beside the other two families (they touch disjoint jobs), so that one
+// family's waves fill the issue slots another leaves idle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +37,7 @@ using namespace spinlat::host;
 namespace {
 
 constexpr uint64_t kDefaultMaxWG = 1ull << 20;
-constexpr size_t kGraphCache = 8;
+constexpr size_t kGraphCache = 16;
 
 uint64_t max_wg(const sl_batch_config* c) { return c->max_workgroups ? c->max_workgroups : kDefaultMaxWG; }
 
@@ -160,9 +162,10 @@ struct sl_batch {
     size_t arena_bytes;
     hipStream_t stream;  // the caller's
     hipStream_t side;    // resident jobs run here, concurrently
+    hipStream_t par;     // the row-group family runs here, beside the others
     hipStream_t cap;     // graph capture only
     hipEvent_t ev_up[2];   // per upload set: its uploads were consumed by the launches
-    hipEvent_t ev_fork, ev_join;
+    hipEvent_t ev_fork, ev_join, ev_par;
     BaseLayout base;
     std::vector<JobHost> jobs;
     FreeList heap;       // free ranges of the job heap
@@ -277,8 +280,12 @@ hipError_t enqueue_family(sl_batch* b, int k, int f, uint64_t n, uint32_t grid, 
 sl_status graph_for(sl_batch* b, int k, uint64_t n, const uint32_t (&grid)[kBatchFamilies], hipGraphExec_t* out)
 {
     const uint64_t key = n * 2 + (uint64_t)k;
-    for (const GraphEntry& g : b->graphs)
-        if (g.key == key && std::equal(grid, grid + kBatchFamilies, g.grid)) {
+    for (size_t i = 0; i < b->graphs.size(); ++i)
+        if (b->graphs[i].key == key && std::equal(grid, grid + kBatchFamilies, b->graphs[i].grid)) {
+            // most recently used last: eviction takes the front
+            const GraphEntry g = b->graphs[i];
+            b->graphs.erase(b->graphs.begin() + (long)i);
+            b->graphs.push_back(g);
             *out = g.exec;
             return SL_OK;
         }
@@ -297,8 +304,11 @@ sl_status graph_for(sl_batch* b, int k, uint64_t n, const uint32_t (&grid)[kBatc
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "batch: graph instantiate");
     if (b->graphs.size() >= kGraphCache) {
-        // the oldest graph may still run: wait before destroying it
+        // the least recently used graph may still run: wait before destroying
+        // it (graphs of earlier calls run on the caller's stream or on par,
+        // which the caller's stream joins at the end of every call)
         e = hipStreamSynchronize(b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->par);
         if (e != hipSuccess) return hip_fail(e, "batch: synchronise before graph eviction");
         (void)hipGraphExecDestroy(b->graphs.front().exec);
         b->graphs.erase(b->graphs.begin());
@@ -359,9 +369,10 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
     b->arena_bytes = arena_bytes;
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->side = nullptr;
+    b->par = nullptr;
     b->cap = nullptr;
     b->ev_up[0] = b->ev_up[1] = nullptr;
-    b->ev_fork = b->ev_join = nullptr;
+    b->ev_fork = b->ev_join = b->ev_par = nullptr;
     b->base = base;
     b->jobs.resize(cfg->max_jobs);
     const size_t heap = round_up(base.heap, kAlign);
@@ -383,10 +394,12 @@ sl_status sl_batch_create(const sl_batch_config* cfg, void* device_arena, size_t
                           hipHostMallocDefault);
     // the library's own streams keep the default priority
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->par, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->ev_up[k], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_par, hipEventDisableTiming);
     if (e != hipSuccess) {
         sl_batch_destroy(b);
         return hip_fail(e, "batch: pinned staging, streams and events");
@@ -465,6 +478,7 @@ sl_status sl_batch_add(sl_batch* b, const sl_params* params, uint64_t sweeps, ui
 
 sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
 {
+    const TraceRange range("sl_batch_sweep");
     if (!b) return fail(SL_E_INVALID, "NULL batch");
     if (n == 0) return SL_OK;
     const uint32_t cap = b->cfg.record_capacity;
@@ -548,10 +562,15 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     if (e != hipSuccess) return hip_fail(e, "batch: upload");
     ++b->calls;
 
+    // the row-group family gets a stream of its own when another family runs
+    const bool split = count[1] && (count[0] || count[2]);
+    if (nres || split) {
+        e = hipEventRecord(b->ev_fork, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch: fork");
+    }
     // resident jobs: one launch on the side stream, overlapping the rest
     if (nres) {
-        e = hipEventRecord(b->ev_fork, b->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
         if (e == hipSuccess)
             e = launch_batch_resident(d_jobs(b), reinterpret_cast<const uint32_t*>(du + u.dyn),
                                       reinterpret_cast<const uint32_t*>(du + u.res), (uint32_t)nres, b->side);
@@ -560,18 +579,36 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     }
     // the other jobs: n_eff sweeps of per-family launches, replayed from a graph
     if (nwg) {
-        uint32_t grid[kBatchFamilies];
-        for (int f = 0; f < kBatchFamilies; ++f) grid[f] = bucket(count[f]);
+        // grids per stream: a family with grid 0 is not launched
+        uint32_t g_main[kBatchFamilies], g_par[kBatchFamilies] = {0, 0, 0};
+        for (int f = 0; f < kBatchFamilies; ++f) g_main[f] = bucket(count[f]);
+        if (split) {
+            g_par[1] = g_main[1];
+            g_main[1] = 0;
+            e = hipStreamWaitEvent(b->par, b->ev_fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch: fork");
+        }
         if (b->cfg.flags & SL_BATCH_NO_GRAPH) {
-            for (int f = 0; f < kBatchFamilies && e == hipSuccess; ++f)
-                e = enqueue_family(b, k, f, n_eff, grid[f], b->stream);
+            for (int f = 0; f < kBatchFamilies && e == hipSuccess; ++f) {
+                if (g_par[f]) e = enqueue_family(b, k, f, n_eff, g_par[f], b->par);
+                if (e == hipSuccess && g_main[f]) e = enqueue_family(b, k, f, n_eff, g_main[f], b->stream);
+            }
             if (e != hipSuccess) return hip_fail(e, "batch sweep");
         } else {
-            hipGraphExec_t exec = nullptr;
-            sl_status gs = graph_for(b, k, n_eff, grid, &exec);
+            // both graphs first (a lookup never evicts the graph it returns or
+            // one used since), then the launches
+            hipGraphExec_t x_par = nullptr, x_main = nullptr;
+            sl_status gs = split ? graph_for(b, k, n_eff, g_par, &x_par) : SL_OK;
+            if (gs == SL_OK && (g_main[0] || g_main[1] || g_main[2])) gs = graph_for(b, k, n_eff, g_main, &x_main);
             if (gs != SL_OK) return gs;
-            e = hipGraphLaunch(exec, b->stream);
+            if (x_par) e = hipGraphLaunch(x_par, b->par);
+            if (e == hipSuccess && x_main) e = hipGraphLaunch(x_main, b->stream);
             if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
+        }
+        if (split) {
+            e = hipEventRecord(b->ev_par, b->par);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_par, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch: join the row-group stream");
         }
     }
     if (nres) {
@@ -628,6 +665,7 @@ sl_status sl_batch_measure(sl_batch* b, uint32_t job_id, sl_record* out, size_t 
 
 sl_status sl_batch_drain(sl_batch* b, sl_record* out, uint32_t* job_of, size_t cap, size_t* n_out)
 {
+    const TraceRange range("sl_batch_drain");
     if (!b) return fail(SL_E_INVALID, "NULL batch");
     if (n_out) *n_out = 0;
     uint64_t total = 0;
@@ -702,12 +740,15 @@ sl_status sl_batch_destroy(sl_batch* b)
     if (!b) return fail(SL_E_INVALID, "NULL batch");
     hipError_t e = hipStreamSynchronize(b->stream);
     if (b->side) (void)hipStreamSynchronize(b->side);
+    if (b->par) (void)hipStreamSynchronize(b->par);
     for (GraphEntry& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     for (int k = 0; k < 2; ++k)
         if (b->ev_up[k]) (void)hipEventDestroy(b->ev_up[k]);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->ev_par) (void)hipEventDestroy(b->ev_par);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->par) (void)hipStreamDestroy(b->par);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->h_jobs) (void)hipHostFree(b->h_jobs);
     for (int k = 0; k < 2; ++k)

@@ -516,6 +516,7 @@ sl_status sl_get_launch(const sl_lattice* h, sl_launch* launch)
 
 sl_status sl_sweep(sl_lattice* h, uint64_t n)
 {
+    const TraceRange range("sl_sweep");
     if (!h) return fail(SL_E_INVALID, "NULL lattice");
     if (n == 0) return SL_OK;
     sl_status st = check_sweep_count(h->pending, h->params.record_capacity, h->next_t,
@@ -526,6 +527,7 @@ sl_status sl_sweep(sl_lattice* h, uint64_t n)
 
 sl_status sl_measure(sl_lattice* h, sl_record* out, size_t cap, size_t* n_out)
 {
+    const TraceRange range("sl_measure");
     if (!h) return fail(SL_E_INVALID, "NULL lattice");
     if (n_out) *n_out = 0;
     const uint64_t n = h->pending;
