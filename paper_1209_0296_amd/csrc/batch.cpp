@@ -517,7 +517,7 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
                               (uint32_t)kBatchKindNeCoupled})
             for (int dim : {2, 3})
                 for (uint32_t v = 0; v < 16; ++v) {
-                    if (v == kBvResident || batch_family(v) != fam) continue;
+                    if (v == kBvResident || batch_family(v, kind) != fam) continue;
                     for (uint32_t j = 0; j < top; ++j) {
                         const JobHost& J = b->jobs[j];
                         if (!J.used || !budget[j] || (uint32_t)class_kind(J) != kind || J.params.dim != dim ||
@@ -562,8 +562,9 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     if (e != hipSuccess) return hip_fail(e, "batch: upload");
     ++b->calls;
 
-    // the row-group family gets a stream of its own when another family runs
-    const bool split = count[1] && (count[0] || count[2]);
+    // the row-group families get a stream of their own when another family runs
+    const bool rows_work = count[1] || count[3], other_work = count[0] || count[2];
+    const bool split = rows_work && other_work;
     if (nres || split) {
         e = hipEventRecord(b->ev_fork, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch: fork");
@@ -580,11 +581,14 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     // the other jobs: n_eff sweeps of per-family launches, replayed from a graph
     if (nwg) {
         // grids per stream: a family with grid 0 is not launched
-        uint32_t g_main[kBatchFamilies], g_par[kBatchFamilies] = {0, 0, 0};
+        uint32_t g_main[kBatchFamilies], g_par[kBatchFamilies] = {};
         for (int f = 0; f < kBatchFamilies; ++f) g_main[f] = bucket(count[f]);
         if (split) {
-            g_par[1] = g_main[1];
-            g_main[1] = 0;
+            for (int f = 0; f < kBatchFamilies; ++f)
+                if (row_family(f)) {
+                    g_par[f] = g_main[f];
+                    g_main[f] = 0;
+                }
             e = hipStreamWaitEvent(b->par, b->ev_fork, 0);
             if (e != hipSuccess) return hip_fail(e, "batch: fork");
         }
@@ -599,7 +603,8 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
             // one used since), then the launches
             hipGraphExec_t x_par = nullptr, x_main = nullptr;
             sl_status gs = split ? graph_for(b, k, n_eff, g_par, &x_par) : SL_OK;
-            if (gs == SL_OK && (g_main[0] || g_main[1] || g_main[2])) gs = graph_for(b, k, n_eff, g_main, &x_main);
+            if (gs == SL_OK && std::any_of(g_main, g_main + kBatchFamilies, [](uint32_t g) { return g != 0; }))
+                gs = graph_for(b, k, n_eff, g_main, &x_main);
             if (gs != SL_OK) return gs;
             if (x_par) e = hipGraphLaunch(x_par, b->par);
             if (e == hipSuccess && x_main) e = hipGraphLaunch(x_main, b->stream);

@@ -66,12 +66,19 @@ inline uint32_t batch_class(int kind, int dim, uint32_t variant)
     return (uint32_t)kind * 32u + (uint32_t)(dim - 2) * 16u + variant;
 }
 
-// Kernel families of the non-resident classes and their work-list segments.
-constexpr int kBatchFamilies = 3;  // 0: walks and windows, 1: row groups, 2: fused
-inline int batch_family(uint32_t variant)
+// Kernel families of the non-resident classes and their work-list segments:
+// 0 walks and windows, 1 row groups of spin-1/2 jobs, 2 fused, 3 row groups of
+// spin-1 jobs (two Philox calls per word need more registers; apart, the
+// spin-1/2 row groups keep more waves per SIMD).
+constexpr int kBatchFamilies = 4;
+inline int batch_family(uint32_t variant, uint32_t kind)
 {
-    return variant >= kBvFusedD4 && variant <= kBvFusedD1 ? 2 : variant >= kBvRowsD4 && variant <= kBvRowsD1 ? 1 : 0;
+    if (variant >= kBvFusedD4 && variant <= kBvFusedD1) return 2;
+    if (variant >= kBvRowsD4 && variant <= kBvRowsD1) return kind == (uint32_t)KIND_ISING_ONE ? 3 : 1;
+    return 0;
 }
+// Families that run on the row-group stream.
+inline bool row_family(int f) { return f == 1 || f == 3; }
 
 // One family's launch: meta holds {count, offset} of each family's segment of
 // `wgs` (valid entries out of `grid` workgroups); the call's sweep number

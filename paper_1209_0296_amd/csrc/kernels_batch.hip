@@ -136,7 +136,7 @@ union BatchLds {
 
 // Kernel families: each launch runs one family's variants only, so its
 // register budget is that of its own bodies.
-constexpr int kFamHalf = 0, kFamRows = 1, kFamFused = 2;
+constexpr int kFamHalf = 0, kFamRows = 1, kFamFused = 2, kFamRowsOne = 3;
 
 template <int FAM, int KIND, int DIM>
 __device__ __forceinline__ void dispatch(uint32_t v, const BatchJob& J, const uint32_t* dj, const BatchWG w,
@@ -150,7 +150,7 @@ __device__ __forceinline__ void dispatch(uint32_t v, const BatchJob& J, const ui
         else if constexpr (KIND != KIND_NE_COUPLED) {
             if (v == kBvWindow) batch_window_body<KIND, DIM>(J, dj, w, colour, step, lds.win);
         }
-    } else if constexpr (FAM == kFamRows) {
+    } else if constexpr (FAM == kFamRows || FAM == kFamRowsOne) {
         if (v == kBvRowsD4) batch_rows_body<KIND, DIM, 4>(J, dj, w, colour, step, lds.row);
         else if (v == kBvRowsD2) batch_rows_body<KIND, DIM, 2>(J, dj, w, colour, step, lds.row);
         else if (v == kBvRowsD1) batch_rows_body<KIND, DIM, 1>(J, dj, w, colour, step, lds.row);
@@ -178,12 +178,17 @@ __global__ void __launch_bounds__(256) k_batch_family(const BatchJob* __restrict
     if (step >= dj[2]) return;  // whole workgroup: no sweep left for this job in this call
     const BatchJob& J = jobs[w.job];
     const uint32_t kind = J.cls >> 5, dim3d = (J.cls >> 4) & 1u, v = J.cls & 15u;
-    if (kind == KIND_ISING_HALF) {
+    if constexpr (FAM == kFamRowsOne) {
+        // row groups of spin-1 jobs only (the row class is 3D)
+        dispatch<FAM, KIND_ISING_ONE, 3>(v, J, dj, w, colour, step, lds, xch);
+    } else if (kind == KIND_ISING_HALF) {
         if (dim3d) dispatch<FAM, KIND_ISING_HALF, 3>(v, J, dj, w, colour, step, lds, xch);
         else dispatch<FAM, KIND_ISING_HALF, 2>(v, J, dj, w, colour, step, lds, xch);
     } else if (kind == KIND_ISING_ONE) {
-        if (dim3d) dispatch<FAM, KIND_ISING_ONE, 3>(v, J, dj, w, colour, step, lds, xch);
-        else dispatch<FAM, KIND_ISING_ONE, 2>(v, J, dj, w, colour, step, lds, xch);
+        if constexpr (FAM != kFamRows) {  // spin-1 row groups are family kFamRowsOne
+            if (dim3d) dispatch<FAM, KIND_ISING_ONE, 3>(v, J, dj, w, colour, step, lds, xch);
+            else dispatch<FAM, KIND_ISING_ONE, 2>(v, J, dj, w, colour, step, lds, xch);
+        }
     } else if (kind == KIND_NE) {
         dispatch<FAM, KIND_NE, 2>(v, J, dj, w, colour, step, lds, xch);
     } else {
@@ -328,6 +333,9 @@ hipError_t launch_batch_family(int family, const BatchJob* jobs, const uint32_t*
         hipLaunchKernelGGL(k_batch_family<kFamHalf>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour, step);
     else if (family == kFamRows)
         hipLaunchKernelGGL(k_batch_family<kFamRows>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour, step);
+    else if (family == kFamRowsOne)
+        hipLaunchKernelGGL(k_batch_family<kFamRowsOne>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour,
+                           step);
     else
         hipLaunchKernelGGL(k_batch_family<kFamFused>, dim3(grid), dim3(256), 0, s, jobs, dyn, wgs, meta, colour,
                            step);
