@@ -66,18 +66,31 @@ class Server:
 
     def run(self, requests, realtime: bool = True):
         """Serve `requests` (sorted by arrival).  With realtime=False every
-        request counts as arrived at time 0 (a closed batch)."""
+        request counts as arrived at time 0 (a closed batch).
+
+        Each round drains the records of everything enqueued so far (the one
+        synchronisation), frees the jobs whose last sweeps ran in the previous
+        chunk, admits what fits, enqueues the next chunk, and only then does
+        the host bookkeeping, so that it overlaps the GPU's work."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         b = self.batch
         queue = deque()
-        active = {}      # job id -> request
+        active = {}      # job id -> request, until its outcome is complete
         parts = {}       # request id -> list of record arrays
         admitted = {}
         outcomes = {}
+        retiring = []    # jobs given all their sweeps: complete at the next drain
         nxt = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         while len(outcomes) < len(reqs):
+            got = b.drain()
+            done_at = now()
+            # requests of the drained records, before a freed slot is reused
+            owner = {jid: active[jid] for jid in got}
+            finishing = [active.pop(jid) for jid in retiring]
+            for jid in retiring:
+                b.remove(jid)  # the stream is idle after the drain
             t = now()
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= t):
                 queue.append(reqs[nxt])
@@ -91,23 +104,21 @@ class Server:
                 active[jid] = r
                 parts[r.id] = []
                 admitted[r.id] = now()
-            if not active:
-                if nxt < len(reqs):
-                    time.sleep(max(0.0, reqs[nxt].arrival - now()))
-                    continue
-                raise RuntimeError("request does not fit an empty arena")
-            b.sweep(self.chunk)
-            got = b.drain()
-            done_at = now()
+            working = list(active)
+            if working:
+                b.sweep(self.chunk)
+            # host bookkeeping while the chunk runs
             for jid, recs in got.items():
-                parts[active[jid].id].append(recs)
-            for jid in list(active):
-                done, remaining, pending = b.status(jid)
-                if remaining == 0 and pending == 0:
-                    r = active.pop(jid)
-                    b.remove(jid)
-                    outcomes[r.id] = Outcome(np.vstack(parts.pop(r.id)), r.arrival,
-                                             admitted[r.id], done_at)
+                parts[owner[jid].id].append(recs)
+            for r in finishing:
+                outcomes[r.id] = Outcome(np.vstack(parts.pop(r.id)), r.arrival, admitted[r.id], done_at)
+            retiring = [jid for jid in working if b.status(jid)[1] == 0]
+            if not working and len(outcomes) < len(reqs):
+                if queue:
+                    raise RuntimeError("request does not fit an empty arena")
+                if nxt >= len(reqs):
+                    raise RuntimeError("server has requests left but nothing to run")
+                time.sleep(max(0.0, reqs[nxt].arrival - now()))
         return outcomes, summarize(outcomes, 0.0, now())
 
     def close(self):
