@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 2D L=64 and L=32768, 3D L=256 and NE L=4096 lines")
-    ap.add_argument("--cpu-sweeps", type=int, default=30)
+    ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--served-jobs", type=int, default=4096,
                     help="jobs in the served Poisson stream (0: skip serving)")
     ap.add_argument("--served-load", type=float, default=0.7,
