@@ -29,7 +29,7 @@ def candidates(p: Params):
         for H in (2, 4, 8, 16):
             for D in (1, 2, 4):
                 out.append((mode, H, D))
-    for waves in (4, 16):
+    for waves in (4, 8, 16):
         for D in (1, 2, 4):
             out.append((MODE_HALF_ROWS, waves, D))
     out.append((MODE_HALF_WINDOW, 0, 0))

@@ -315,8 +315,9 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
                                              const Vec<D>& up, const Vec<D>& down, const Vec<D>* zm,
                                              const Vec<D>* zp, uint32_t g0, uint32_t colour, uint32_t t,
                                              const PhiloxKey& ks, const RowLuts& lut, uint64_t thr_up,
-                                             uint64_t thr_down, bool count, Obs& o)
+                                             uint64_t thr_down, bool count, Obs& o, const Words4* pre = nullptr)
 {
+    // pre: the words' Philox outputs (spin-1: two per word), when the caller drew them
     constexpr int z = 2 * DIM;
     Vec<D> out;
 #pragma unroll
@@ -326,7 +327,7 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
             uint32_t S = same.w[d] + side[d] + up.w[d] + down.w[d];
             if constexpr (DIM == 3) S += zm->w[d] + zp->w[d];
             if constexpr (KIND == KIND_ISING_HALF) {
-                const Words4 w = philox4x32_10(g, colour, t, 0u, ks);
+                const Words4 w = pre ? pre[d] : philox4x32_10(g, colour, t, 0u, ks);
                 out.w[d] = half_word(own.w[d], S, w, reinterpret_cast<const uint8_t*>(lut.e), z);
                 if (count) {
                     o.acc += __builtin_popcount(own.w[d] ^ out.w[d]);
@@ -338,8 +339,8 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
                     }
                 }
             } else {
-                const Words4 wa = philox4x32_10(2 * g, colour, t, 0u, ks);
-                const Words4 wb = philox4x32_10(2 * g + 1, colour, t, 0u, ks);
+                const Words4 wa = pre ? pre[2 * d] : philox4x32_10(2 * g, colour, t, 0u, ks);
+                const Words4 wb = pre ? pre[2 * d + 1] : philox4x32_10(2 * g + 1, colour, t, 0u, ks);
                 int nacc = 0;
                 out.w[d] = one_word<DIM>(own.w[d], S, wa, wb, lut, nacc);
                 if (count) {

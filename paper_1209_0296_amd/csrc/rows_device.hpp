@@ -73,7 +73,8 @@ __device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a
 template <int KIND, int DIM, int D, int P>
 __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
                                             const RowsAt& at, const Lanes& ln, const PhiloxKey& ks,
-                                            const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o)
+                                            const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o,
+                                            const Words4* pre)
 {
     const uint64_t row = (uint64_t)at.z * rg.L + at.y;
     const uint64_t cb = 4ull * D * ln.pos;
@@ -90,7 +91,7 @@ __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const Swee
     }
     const uint32_t g0 = (uint32_t)(row * rg.ncols + (uint64_t)D * ln.pos);
     const Vec<D> nw = row_update<KIND, DIM, D, P>(in.own, q0, side, qm, qp, &qzm, &qzp, g0, a.colour, a.t, ks, lut,
-                                                  thr_up, thr_down, true, o);
+                                                  thr_up, thr_down, true, o, pre);
     stv<D>(colour_array(a, a.colour), row * rg.Lh + cb, nw);
 }
 
@@ -100,12 +101,26 @@ __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepA
                                           uint64_t thr_up, uint64_t thr_down, Obs& o)
 {
     if (!at.ok) return;
+    // Ising: the words' random numbers do not depend on the lattice, so they
+    // are drawn here, before the first use of the loaded rows, while the loads
+    // are still in flight (the scheduling barrier keeps that order).  Spin-1
+    // with four words per lane would hold 32 words and spill: it draws late.
+    constexpr bool kPre = KIND == KIND_ISING_HALF || (KIND == KIND_ISING_ONE && D <= 2);
+    constexpr int kCalls = KIND == KIND_ISING_ONE ? 2 : 1;  // Philox calls per word
+    Words4 pre[kPre ? kCalls * D : 1];
+    if constexpr (kPre) {
+        const uint32_t g0 = (uint32_t)(((uint64_t)at.z * rg.L + at.y) * rg.ncols + (uint64_t)D * ln.pos);
+#pragma unroll
+        for (int i = 0; i < kCalls * D; ++i) pre[i] = philox4x32_10(kCalls * g0 + i, a.colour, a.t, 0u, ks);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const Words4* const pw = kPre ? pre : nullptr;
     // the row parity is uniform across the wave: every row of a row set has
     // the parity of rem & 1
     if (((at.y + at.z + a.colour) & 1u) == 0)
-        rows_update<KIND, DIM, D, 0>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+        rows_update<KIND, DIM, D, 0>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
     else
-        rows_update<KIND, DIM, D, 1>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+        rows_update<KIND, DIM, D, 1>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
 }
 
 // Row groups of one wave at most; the row sets per plane go to nstrips, the

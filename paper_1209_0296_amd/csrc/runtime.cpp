@@ -116,7 +116,9 @@ bool lut32_ok(const sl_lattice* h)
 //     strips with 2 words;
 //   - 3D: half-sweeps by independent row groups, 4 words per lane from L = 128
 //     (L = 256: 18.4 against 19.2 for the walk with 4-row strips; L = 128: 8.8
-//     against 10.6), 1 word below (L = 64: 7.5 against 8.9).
+//     against 10.6), 1 word below (L = 64: 7.5 against 8.9); spin-1/2 takes
+//     blocks of 8 waves from L = 256 (17.3 against 17.6 with 4), else 4 (L =
+//     128: 7.6 against 8.8; spin-1 at 256: 24.7 against 24.9).
 // A fused 3D sweep would recompute a halo in two directions, so 3D uses
 // half-sweeps.  Other widths are tried in order when D does not divide the
 // row, and shapes the whole-row kernels cannot take fall back to the window
@@ -143,10 +145,11 @@ sl_launch auto_launch(const sl_lattice* h)
     sl_launch l{};
     if (h->params.dim == 3) {
         const int Ds[3] = {L >= 128 ? 4 : 1, 2, L >= 128 ? 1 : 4};
+        const int waves = L >= 256 && half_spin ? 8 : 4;
         for (int D : Ds)
-            if (rows_supported(g, h->kind, 4, D, lut32_ok(h))) {
+            if (rows_supported(g, h->kind, waves, D, lut32_ok(h))) {
                 l.mode = SL_MODE_HALF_ROWS;
-                l.tile_rows = 4;
+                l.tile_rows = waves;
                 l.tile_words = D;
                 return l;
             }
