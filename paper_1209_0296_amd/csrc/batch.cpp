@@ -13,12 +13,12 @@
 // staging (double-buffered, so the host never waits for the previous call),
 // runs the resident jobs' launch on a second stream of the library's own
 // while the per-sweep launches of the other jobs run on the caller's stream,
-// and joins the two.  The per-sweep launches of the three kernel families are
+// and joins the two.  The per-sweep launches of the kernel families are
 // captured once per (sweeps, grid buckets) shape into HIP graphs, each on one
 // stream, and replayed; the kernels read the true segment counts from device
-// memory.  The row-group family runs on a third stream of the library's,
-// beside the other two families (they touch disjoint jobs), so that one
-// family's waves fill the issue slots another leaves idle.
+// memory.  The two row-group families run on a third stream of the library's,
+// beside the other families (they touch disjoint jobs), so that one family's
+// waves fill the issue slots another leaves idle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -162,7 +162,7 @@ struct sl_batch {
     size_t arena_bytes;
     hipStream_t stream;  // the caller's
     hipStream_t side;    // resident jobs run here, concurrently
-    hipStream_t par;     // the row-group family runs here, beside the others
+    hipStream_t par;     // the row-group families run here, beside the others
     hipStream_t cap;     // graph capture only
     hipEvent_t ev_up[2];   // per upload set: its uploads were consumed by the launches
     hipEvent_t ev_fork, ev_join, ev_par;

@@ -17,10 +17,10 @@
 //     row group (no walk).
 //   - walk / window: one colour per launch, whole-row walks down strips, or
 //     64-lane column windows for rows that fit no wave.
-// The non-resident classes form three kernel families, each with its own
-// kernel so that its register budget is its own: half (walks and windows) and
-// rows launch once per colour, fused once per sweep (all colour work of the
-// fused jobs).  A work list names the workgroups as (job, first item) pairs in
+// The non-resident classes form four kernel families, each with its own
+// kernel so that its register budget is its own: half (walks and windows),
+// rows of spin-1/2 jobs and rows of spin-1 jobs launch once per colour, fused
+// once per sweep (all colour work of the fused jobs).  A work list names the workgroups as (job, first item) pairs in
 // one segment per family, sorted by class, so a workgroup touches one job and
 // its reduction goes to that job's record.  The number of valid entries and
 // the offset of each segment are read from device memory, so a grid rounded
