@@ -220,3 +220,27 @@ def test_job_table_full_is_not_an_error():
     assert stats["jobs"] == len(reqs)
     for r in reqs:
         np.testing.assert_array_equal(outcomes[r.id].records, run_oracle(r.params, r.sweeps)[1])
+
+
+def test_graph_cache_eviction_keeps_results():
+    """More call shapes than the graph cache holds (sweeps per call 1 .. 24 on
+    every family, both streams): evicted graphs are rebuilt and every job still
+    equals the oracle run alone."""
+    jobs = [S.Params(dim=3, L=32, T=4.5, seed=401),              # row groups, spin-1/2
+            S.Params(dim=3, L=40, two_s=2, T=3.0, seed=402),     # row groups, spin-1
+            S.Params(L=512, T=2.3, seed=403),                    # fused
+            S.Params(L=936, T=2.2, seed=404),                    # column windows
+            S.Params(L=64, T=2.0, seed=405)]                     # resident
+    total = sum(range(1, 25))
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=8, record_capacity=32)
+    ids = [b.add(p, sweeps=total) for p in jobs]
+    recs = {i: [] for i in ids}
+    for n in range(1, 25):
+        b.sweep(n)
+        for j, r in b.drain().items():
+            recs[j].append(r)
+    for i, p in zip(ids, jobs):
+        print(f"case eviction job {i} L={p.L} dim={p.dim}", flush=True)
+        assert b.status(i)[:2] == (total, 0)
+        _check_job(b, i, p, recs[i], total)
+    b.close()
