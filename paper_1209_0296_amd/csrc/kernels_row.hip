@@ -82,14 +82,15 @@ void launch_fused_h(const SweepArgs& a, const RowGeom& rg, const uint8_t* s0, co
                            s0, s1, d0, d1);
 }
 
-// Strip heights of the default schedules (2, 4, 8, 16) run the unrolled walk
+// Strip heights of the default schedules (2, 4, 8, 16, 32) run the unrolled walk
 // when they divide L; any other height runs the runtime-height kernel.
 template <int KIND, int D>
 void launch_fused_d(const SweepArgs& a, const RowGeom& rg, const uint8_t* s0, const uint8_t* s1, uint8_t* d0,
                     uint8_t* d1, hipStream_t s)
 {
     const bool whole = rg.L % rg.H == 0;
-    if (whole && rg.H == 16) launch_fused_h<KIND, D, 16>(a, rg, s0, s1, d0, d1, s);
+    if (whole && rg.H == 32) launch_fused_h<KIND, D, 32>(a, rg, s0, s1, d0, d1, s);
+    else if (whole && rg.H == 16) launch_fused_h<KIND, D, 16>(a, rg, s0, s1, d0, d1, s);
     else if (whole && rg.H == 8) launch_fused_h<KIND, D, 8>(a, rg, s0, s1, d0, d1, s);
     else if (whole && rg.H == 4) launch_fused_h<KIND, D, 4>(a, rg, s0, s1, d0, d1, s);
     else if (whole && rg.H == 2) launch_fused_h<KIND, D, 2>(a, rg, s0, s1, d0, d1, s);

@@ -109,11 +109,11 @@ bool lut32_ok(const sl_lattice* h)
 //   - 2D up to L = 1024: fused with 2-row strips, 1 word per lane (L = 1024:
 //     4.9 against 6.1 with 2 words); L = 2048: fused, 2-row strips, 2 words;
 //   - 2D L = 4096: fused, 4-row strips, 2 words (spin-1/2: 14.6 against 17.7
-//     with 4 words); from L = 8192 spin-1/2 takes 16-row strips, with 2 words
-//     per lane below L = 16384 (8192: 38.3 against 39.8 with 8-row strips
-//     and 4 words, 40.5 with 16 rows and 4 words) and 4 words from 16384
-//     (145.8 against 153.9 with 8-row strips); spin-1 and NE keep 4-row
-//     strips with 2 words;
+//     with 4 words); L = 8192 spin-1/2 takes 16-row strips with 2 words per
+//     lane (38.3 against 39.8 with 8-row strips and 4 words, 40.5 with 16
+//     rows and 4 words, 42.2 with 32 rows and 1 word), and from L = 16384
+//     32-row strips with 4 words (16384: 133.7 against 141.4 with 16 rows;
+//     32768: 538 against 569); spin-1 and NE keep 4-row strips with 2 words;
 //   - 3D: half-sweeps by independent row groups, 4 words per lane from L = 128
 //     (L = 256: 18.4 against 19.2 for the walk with 4-row strips; L = 128: 8.8
 //     against 10.6), 1 word below (L = 64: 7.5 against 8.9); spin-1/2 takes
@@ -171,7 +171,7 @@ sl_launch auto_launch(const sl_lattice* h)
         H = 4;
         Ds[0] = 2, Ds[1] = 4, Ds[2] = 1;
     } else if (L >= 16384) {
-        H = 16;
+        H = 32;
     } else {
         H = 16;
         Ds[0] = 2, Ds[1] = 4, Ds[2] = 1;

@@ -18,7 +18,7 @@ T_END = 2 ** 32
 
 SCHEDULES = [(S.MODE_SIMPLE, 0, 0), (S.MODE_HALF, 4, 1), (S.MODE_HALF, 3, 2), (S.MODE_FUSED, 4, 1),
              (S.MODE_FUSED, 5, 2), (S.MODE_HALF_WINDOW, 0, 0), (S.MODE_FUSED_WINDOW, 3, 0),
-             (S.MODE_RESIDENT, 0, 0), (S.MODE_HALF_ROWS, 3, 2), (S.MODE_HALF_ROWS, 0, 4), (S.MODE_FUSED, 8, 4), (S.MODE_FUSED, 16, 2),
+             (S.MODE_RESIDENT, 0, 0), (S.MODE_HALF_ROWS, 3, 2), (S.MODE_HALF_ROWS, 0, 4), (S.MODE_FUSED, 8, 4), (S.MODE_FUSED, 16, 2), (S.MODE_FUSED, 32, 4),
              (S.MODE_AUTO, 0, 0)]
 
 SHAPES = [dict(L=64, T=2.269), dict(L=256, T=2.0), dict(L=40, two_s=2, T=1.5),

@@ -20,7 +20,7 @@ RESIDENT = (S.MODE_RESIDENT, 0, 0)
 # whole-row kernels: (mode, rows per strip, words per lane)
 ROW = [(m, H, D) for m in (S.MODE_HALF, S.MODE_FUSED) for H, D in ((3, 1), (8, 2), (5, 4))]
 # whole-row walks with the unrolled strip heights, and row groups without a walk
-ROW += [(S.MODE_FUSED, 2, 4), (S.MODE_FUSED, 4, 2), (S.MODE_FUSED, 8, 4), (S.MODE_FUSED, 16, 2), (S.MODE_HALF_ROWS, 0, 0),
+ROW += [(S.MODE_FUSED, 2, 4), (S.MODE_FUSED, 4, 2), (S.MODE_FUSED, 8, 4), (S.MODE_FUSED, 16, 2), (S.MODE_FUSED, 32, 4), (S.MODE_HALF_ROWS, 0, 0),
         (S.MODE_HALF_ROWS, 1, 1), (S.MODE_HALF_ROWS, 3, 2), (S.MODE_HALF_ROWS, 16, 4)]
 
 
