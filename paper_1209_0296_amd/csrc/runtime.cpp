@@ -113,7 +113,11 @@ bool lut32_ok(const sl_lattice* h)
 //     lane (38.3 against 39.8 with 8-row strips and 4 words, 40.5 with 16
 //     rows and 4 words, 42.2 with 32 rows and 1 word), and from L = 16384
 //     32-row strips with 4 words (16384: 133.7 against 141.4 with 16 rows;
-//     32768: 538 against 569); spin-1 and NE keep 4-row strips with 2 words;
+//     32768: 538 against 569); spin-1 takes 16-row strips with 2 words from
+//     L = 8192 (68.3 against 80.7 with 4-row strips); NE takes 8-row strips
+//     with 1 word at L = 4096 (17.1 against 17.6 with 4 rows and 2 words)
+//     and 4-row strips with 2 words from 8192; coupled NE keeps 4-row strips
+//     with 2 words;
 //   - 3D: half-sweeps by independent row groups, 4 words per lane from L = 128
 //     (L = 256: 18.4 against 19.2 for the walk with 4-row strips; L = 128: 8.8
 //     against 10.6), 1 word below (L = 64: 7.5 against 8.9); spin-1/2 takes
@@ -167,10 +171,13 @@ sl_launch auto_launch(const sl_lattice* h)
     } else if (L <= 2048) {
         H = 2;
         Ds[0] = 2, Ds[1] = 1, Ds[2] = 4;
-    } else if (!half_spin || L < 8192) {
+    } else if (h->params.model == SL_NORTH_EAST && L < 8192) {
+        H = 8;
+        Ds[0] = 1, Ds[1] = 2, Ds[2] = 4;
+    } else if (L < 8192 || !(half_spin || h->kind == KIND_ISING_ONE)) {
         H = 4;
         Ds[0] = 2, Ds[1] = 4, Ds[2] = 1;
-    } else if (L >= 16384) {
+    } else if (L >= 16384 && half_spin) {
         H = 32;
     } else {
         H = 16;
