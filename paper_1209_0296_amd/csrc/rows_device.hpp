@@ -57,16 +57,18 @@ __device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a
     const uint32_t c = a.colour;
     const uint8_t* O = colour_array(a, c ^ 1u);
     const uint64_t rowb = rg.Lh;
-    const uint64_t cb = 4ull * D * ln.pos;
-    const uint64_t plane = (uint64_t)z * L;
-    const uint64_t row = plane + y;
-    in.own = ldv<D>(colour_array(a, c), row * rowb + cb);
-    in.o0 = ldv<D>(O, row * rowb + cb);
-    in.om = ldv<D>(O, (plane + (y == 0 ? L - 1 : y - 1)) * rowb + cb);
-    in.op = ldv<D>(O, (plane + (y + 1 == L ? 0 : y + 1)) * rowb + cb);
+    // one byte offset for the row, the neighbour rows as signed steps from it
+    // (the periodic wrap as a select); the plane steps are wave-uniform
+    const int64_t base = (int64_t)(((uint64_t)z * L + y) * rowb + 4ull * D * ln.pos);
+    const int64_t ystep = (int64_t)rowb, ywrap = (int64_t)(L - 1) * (int64_t)rowb;
+    in.own = ldv<D>(colour_array(a, c), (uint64_t)base);
+    in.o0 = ldv<D>(O, (uint64_t)base);
+    in.om = ldv<D>(O, (uint64_t)(base + (y == 0 ? ywrap : -ystep)));
+    in.op = ldv<D>(O, (uint64_t)(base + (y + 1 == L ? -ywrap : ystep)));
     if constexpr (DIM == 3) {
-        in.zm = ldv<D>(O, ((uint64_t)(z == 0 ? L - 1 : z - 1) * L + y) * rowb + cb);
-        in.zp = ldv<D>(O, ((uint64_t)(z + 1 == L ? 0 : z + 1) * L + y) * rowb + cb);
+        const int64_t zstep = (int64_t)L * ystep, zwrap = (int64_t)(L - 1) * zstep;
+        in.zm = ldv<D>(O, (uint64_t)(base + (z == 0 ? zwrap : -zstep)));
+        in.zp = ldv<D>(O, (uint64_t)(base + (z + 1 == L ? -zwrap : zstep)));
     }
 }
 
