@@ -318,3 +318,12 @@ def test_zero_sweeps_and_single_record_ring():
     np.testing.assert_array_equal(np.vstack(recs), o_r)
     np.testing.assert_array_equal(lat.spins(), o_s)
     lat.close()
+
+
+@pytest.mark.parametrize("kw", [dict(L=8192, two_s=2, T=1.6935),     # spin-1: 16-row strips, 2 words
+                                dict(L=16384, T=2.269),               # spin-1/2: 32-row strips, 4 words
+                                dict(model=S.NORTH_EAST, L=8192, c=0.1)])
+def test_large_default_schedules(kw):
+    """The default schedules of the large 2D shapes, whole lattice and records."""
+    sp = S.Params(seed=7, record_capacity=4, **kw)
+    _check(sp, 2, launch=AUTO, nthreads=16)
