@@ -149,12 +149,27 @@ __device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, 
     lds_barrier();
     const PhiloxKey ks = philox_schedule(a.key0, a.key1);
     constexpr uint32_t K = 4 / D;  // rg.K
+    if constexpr (D == 1) {
+        // one word per lane leaves registers to spare: both row sets of a
+        // pair are loaded before either is updated, so the second set's loads
+        // overlap the first set's work
 #pragma nounroll
-    for (uint32_t k = 0; k < K; ++k) {
-        const RowsAt at = rows_at(rg, it0 + k, ln.slot);
-        RowsIn<DIM, D> in;
-        rows_load<DIM, D>(in, a, rg, at, ln);
-        rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+        for (uint32_t k = 0; k < K; k += 2) {
+            const RowsAt at0 = rows_at(rg, it0 + k, ln.slot), at1 = rows_at(rg, it0 + k + 1, ln.slot);
+            RowsIn<DIM, D> in0, in1;
+            rows_load<DIM, D>(in0, a, rg, at0, ln);
+            rows_load<DIM, D>(in1, a, rg, at1, ln);
+            rows_step<KIND, DIM, D>(in0, a, rg, at0, ln, ks, lut, thr_up, thr_down, o);
+            rows_step<KIND, DIM, D>(in1, a, rg, at1, ln, ks, lut, thr_up, thr_down, o);
+        }
+    } else {
+#pragma nounroll
+        for (uint32_t k = 0; k < K; ++k) {
+            const RowsAt at = rows_at(rg, it0 + k, ln.slot);
+            RowsIn<DIM, D> in;
+            rows_load<DIM, D>(in, a, rg, at, ln);
+            rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+        }
     }
 }
 
