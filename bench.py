@@ -364,19 +364,29 @@ def main():
                                 # committed counters, while the kernel sources match them
                                 "traffic": measured_traffic(key),
                                 "valu": valu_fraction(key, per_launch_s)})
+    # the served and CPU-baseline sections report an exception in the line
+    # instead of losing the headline measurement taken above
     served_res = None
     if args.served_jobs > 0:
-        served_res = served(args)
-        print(f"# served: capacity {served_res['capacity']['jobs_per_s']:.4g} jobs/s "
-              f"({served_res['capacity']['attempts_per_s']:.3g} attempts/s); at "
-              f"{served_res['offered_load']:.0%} load p50 {served_res['p50_latency_s']} s, "
-              f"p99 {served_res['p99_latency_s']} s", file=sys.stderr, flush=True)
+        try:
+            served_res = served(args)
+            print(f"# served: capacity {served_res['capacity']['jobs_per_s']:.4g} jobs/s "
+                  f"({served_res['capacity']['attempts_per_s']:.3g} attempts/s); at "
+                  f"{served_res['offered_load']:.0%} load p50 {served_res['p50_latency_s']} s, "
+                  f"p99 {served_res['p99_latency_s']} s", file=sys.stderr, flush=True)
+        except Exception as e:  # noqa: BLE001
+            served_res = {"error": f"{type(e).__name__}: {e}"}
+            print(f"# served: failed: {served_res['error']}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
-        threads = baseline_threads()
-        cpu = cpu_baseline(cfg2, args.cpu_sweeps, threads)
-        print(f"# oracle: {cpu['value']:.4g} attempts/s on {threads} threads", file=sys.stderr,
-              flush=True)
+        try:
+            threads = baseline_threads()
+            cpu = cpu_baseline(cfg2, args.cpu_sweeps, threads)
+            print(f"# oracle: {cpu['value']:.4g} attempts/s on {threads} threads", file=sys.stderr,
+                  flush=True)
+        except Exception as e:  # noqa: BLE001
+            cpu = {"error": f"{type(e).__name__}: {e}"}
+            print(f"# oracle: failed: {cpu['error']}", file=sys.stderr, flush=True)
 
     roof = dict(main_res["roofline"])
     roof["traffic"] = measured_traffic("ising2d_L8192")
