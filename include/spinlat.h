@@ -169,7 +169,11 @@ typedef enum sl_mode {
                                  its neighbour rows, no walk; tile_rows = waves per
                                  workgroup, 1..16 (0: 4), tile_words D in {1, 2, 4} (0:
                                  widest that fits); the colour row must fit one wave:
-                                 L / (8 D) <= 64.  The default for 3D lattices that fit */
+                                 ceil(L / (8 D)) <= 64.  Ising lattices may have rows that
+                                 D does not divide (then at least two lanes per row; the
+                                 last lane holds the row's last D words); NE lattices need
+                                 L / 8 divisible by D.  The default for 3D lattices that
+                                 fit */
 } sl_mode;
 
 typedef struct sl_launch {

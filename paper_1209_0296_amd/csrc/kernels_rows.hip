@@ -36,17 +36,20 @@ void launch_rows_k(const SweepArgs& a, const RowGeom& rg, hipStream_t s)
 
 }  // namespace
 
+// Ising rows may be ragged (D need not divide the row's word count); the NE
+// kinds' observables are not masked for it.
 bool rows_supported(const Geom& g, int kind, int waves, int tile_words, bool lut32_ok)
 {
     if (kind == KIND_ISING_HALF && !lut32_ok) return false;
     RowGeom rg;
-    return make_rows_geom(g, tile_words, waves, rg);
+    return make_rows_geom(g, tile_words, waves, rg, kind == KIND_ISING_HALF || kind == KIND_ISING_ONE);
 }
 
 hipError_t launch_rows_half(const SweepArgs& a, int kind, int waves, int D, hipStream_t s)
 {
     RowGeom rg;
-    if (!make_rows_geom(a.g, D, waves, rg)) return hipErrorInvalidValue;
+    if (!make_rows_geom(a.g, D, waves, rg, kind == KIND_ISING_HALF || kind == KIND_ISING_ONE))
+        return hipErrorInvalidValue;
     if (a.g.dim == 2) {
         if (kind == KIND_ISING_HALF) launch_rows_k<KIND_ISING_HALF, 2>(a, rg, s);
         else if (kind == KIND_ISING_ONE) launch_rows_k<KIND_ISING_ONE, 2>(a, rg, s);

@@ -48,6 +48,8 @@ struct RowGeom {
     uint32_t block;   // threads per block
     uint32_t rdiv;    // ceil(2^16 / R): lane / R == (lane * rdiv) >> 16 for every lane < 64
     uint32_t K;       // row sets per wave (row-group kernels)
+    uint32_t rag;     // row-group kernels: words of the row in the last lane when D does not
+                      // divide ncols (then 1 .. D-1), else 0
 };
 
 __host__ __device__ inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
@@ -111,6 +113,7 @@ __device__ __forceinline__ void stv(uint8_t* base, uint64_t off, const Vec<D>& v
 // (periodic within the row group).
 struct Lanes {
     uint32_t lane, wave, slot, pos, src_l, src_r;  // wave is wave-uniform
+    uint32_t col0;  // first word of the row this lane holds (D * pos but in a ragged last lane)
 };
 
 template <bool XW, int P>
@@ -310,14 +313,19 @@ __device__ __forceinline__ uint32_t ne_word(uint32_t own, uint32_t north, uint32
 
 // Update the D words of one lane in one row.  Neighbour words are prepared;
 // `side` are the prepared same-row neighbours aligned to the words.
-template <int KIND, int DIM, int D, int P>
+// RAG (Ising kinds): the first `uncounted` words of this lane are also held,
+// and counted, by another lane; they are updated and stored alike but left
+// out of the observables.
+template <int KIND, int DIM, int D, int P, bool RAG = false>
 __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& same, const uint32_t (&side)[D],
                                              const Vec<D>& up, const Vec<D>& down, const Vec<D>* zm,
                                              const Vec<D>* zp, uint32_t g0, uint32_t colour, uint32_t t,
                                              const PhiloxKey& ks, const RowLuts& lut, uint64_t thr_up,
-                                             uint64_t thr_down, bool count, Obs& o, const Words4* pre = nullptr)
+                                             uint64_t thr_down, bool count, Obs& o, const Words4* pre = nullptr,
+                                             uint32_t uncounted = 0)
 {
     // pre: the words' Philox outputs (spin-1: two per word), when the caller drew them
+    static_assert(!RAG || KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE, "ragged rows: Ising kinds");
     constexpr int z = 2 * DIM;
     Vec<D> out;
 #pragma unroll
@@ -330,12 +338,18 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
                 const Words4 w = pre ? pre[d] : philox4x32_10(g, colour, t, 0u, ks);
                 out.w[d] = half_word(own.w[d], S, w, reinterpret_cast<const uint8_t*>(lut.e), z);
                 if (count) {
-                    o.acc += __builtin_popcount(own.w[d] ^ out.w[d]);
+                    uint32_t ow = out.w[d], iw = own.w[d];
+                    if constexpr (RAG) {
+                        const uint32_t m = (uint32_t)d < uncounted ? 0u : ~0u;
+                        ow &= m;
+                        iw &= m;
+                    }
+                    o.acc += __builtin_popcount(iw ^ ow);
                     if (colour == 0) {
-                        o.mag0 = dot4(out.w[d], 0x01010101u, o.mag0);
+                        o.mag0 = dot4(ow, 0x01010101u, o.mag0);
                     } else {
-                        o.mag1 = dot4(out.w[d], 0x01010101u, o.mag1);
-                        o.dd = dot4(out.w[d], S, o.dd);
+                        o.mag1 = dot4(ow, 0x01010101u, o.mag1);
+                        o.dd = dot4(ow, S, o.dd);
                     }
                 }
             } else {
@@ -344,12 +358,18 @@ __device__ __forceinline__ Vec<D> row_update(const Vec<D>& own, const Vec<D>& sa
                 int nacc = 0;
                 out.w[d] = one_word<DIM>(own.w[d], S, wa, wb, lut, nacc);
                 if (count) {
+                    uint32_t ow = out.w[d];
+                    if constexpr (RAG) {
+                        const uint32_t m = (uint32_t)d < uncounted ? 0u : ~0u;
+                        ow &= m;
+                        nacc &= (int)m;
+                    }
                     o.acc += nacc;
                     if (colour == 0) {
-                        o.mag0 = dot4(out.w[d], 0x01010101u, o.mag0);
+                        o.mag0 = dot4(ow, 0x01010101u, o.mag0);
                     } else {
-                        o.mag1 = dot4(out.w[d], 0x01010101u, o.mag1);
-                        o.dd = dot4(out.w[d], S, o.dd);
+                        o.mag1 = dot4(ow, 0x01010101u, o.mag1);
+                        o.dd = dot4(ow, S, o.dd);
                     }
                 }
             }
@@ -409,6 +429,7 @@ __device__ __forceinline__ Lanes lanes_of(const RowGeom& rg, bool xw)
         ln.slot = 0;
         ln.pos = threadIdx.x;
         ln.src_l = ln.src_r = 0;
+        ln.col0 = rg.D * ln.pos;
     } else {
         const uint32_t slot = __umul24(ln.lane, rg.rdiv) >> 16;  // ln.lane / rg.R
         ln.slot = slot;
@@ -416,6 +437,8 @@ __device__ __forceinline__ Lanes lanes_of(const RowGeom& rg, bool xw)
         const uint32_t base = slot * rg.R;
         ln.src_l = base + (ln.pos == 0 ? rg.R - 1 : ln.pos - 1);
         ln.src_r = base + (ln.pos + 1 == rg.R ? 0 : ln.pos + 1);
+        // a ragged row's last lane holds the row's last D words, rag of them its own
+        ln.col0 = rg.D * ln.pos - (rg.rag != 0 && ln.pos + 1 == rg.R ? rg.D - rg.rag : 0u);
     }
     return ln;
 }
@@ -698,18 +721,22 @@ __device__ __forceinline__ void fused_item(const SweepArgs& a, const RowGeom& rg
     }
 }
 
-// Host: whole-row geometry for strip height H and D words per lane.
-inline bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg)
+// Host: whole-row geometry for strip height H and D words per lane.  With
+// `ragged` (row-group kernels only) D need not divide the row: the group has
+// ceil(ncols / D) >= 2 lanes, at most one wave, and its last lane holds the
+// row's last D words, of which rg.rag are its own.
+inline bool make_row_geom(const Geom& g, int H, int D, bool fused, RowGeom& rg, bool ragged = false)
 {
     rg = RowGeom{};
     rg.L = g.L;
     rg.Lh = g.Lh;
     rg.ncols = g.Lh / 4;
     if (D != 1 && D != 2 && D != 4) return false;
-    if (rg.ncols % (uint32_t)D) return false;
     rg.D = (uint32_t)D;
-    rg.R = rg.ncols / rg.D;
-    if (rg.R == 0) return false;
+    rg.rag = rg.ncols % rg.D;
+    if (rg.rag && !ragged) return false;
+    rg.R = cdiv(rg.ncols, rg.D);
+    if (rg.R == 0 || (rg.rag && (rg.R < 2 || rg.R > 64))) return false;
     rg.rdiv = (65536u + rg.R - 1u) / rg.R;
     if (rg.R <= 64) {
         rg.slots = 64 / rg.R;

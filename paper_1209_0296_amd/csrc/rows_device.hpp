@@ -59,7 +59,7 @@ __device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a
     const uint64_t rowb = rg.Lh;
     // one byte offset for the row, the neighbour rows as signed steps from it
     // (the periodic wrap as a select); the plane steps are wave-uniform
-    const int64_t base = (int64_t)(((uint64_t)z * L + y) * rowb + 4ull * D * ln.pos);
+    const int64_t base = (int64_t)(((uint64_t)z * L + y) * rowb + 4ull * ln.col0);
     const int64_t ystep = (int64_t)rowb, ywrap = (int64_t)(L - 1) * (int64_t)rowb;
     in.own = ldv<D>(colour_array(a, c), (uint64_t)base);
     in.o0 = ldv<D>(O, (uint64_t)base);
@@ -72,16 +72,35 @@ __device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a
     }
 }
 
-template <int KIND, int DIM, int D, int P>
+// Ragged rows (RAG): ncols = (R - 1) D + rag, and the last lane holds words
+// ncols - D .. ncols - 1, so its first D - rag words are also lane R-2's last
+// ones.  Both copies of such a word see the same neighbours and random
+// numbers, so they store the same value; only lane R-2's copy is counted.  The
+// edge words the lanes pass on change to keep that true: for p = 0 lane R-2
+// passes word rag - 1 (the one before the last lane's first word), for p = 1
+// the last lane passes word D - rag (the one after lane R-2's last word).
+template <int KIND, int DIM, int D, int P, bool RAG>
 __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
                                             const RowsAt& at, const Lanes& ln, const PhiloxKey& ks,
                                             const RowLuts& lut, uint64_t thr_up, uint64_t thr_down, Obs& o,
                                             const Words4* pre)
 {
     const uint64_t row = (uint64_t)at.z * rg.L + at.y;
-    const uint64_t cb = 4ull * D * ln.pos;
+    const uint64_t cb = 4ull * ln.col0;
     const Vec<D> q0 = prepv<KIND, D>(in.o0);
-    const uint32_t x = shift_in<false, P>(q0.w[D - 1], q0.w[0], ln, 0u);
+    uint32_t last = q0.w[D - 1], first = q0.w[0], uncounted = 0;
+    if constexpr (RAG) {
+        const uint32_t r = rg.rag;  // 1 .. D-1, wave-uniform
+        if constexpr (P == 0) {
+            const uint32_t w = D == 2 ? q0.w[0] : (r == 1 ? q0.w[0] : r == 2 ? q0.w[1 % D] : q0.w[2 % D]);
+            if (ln.pos + 2 == rg.R) last = w;
+        } else {
+            const uint32_t w = D == 2 ? q0.w[1 % D] : (r == 1 ? q0.w[3 % D] : r == 2 ? q0.w[2 % D] : q0.w[1 % D]);
+            if (ln.pos + 1 == rg.R) first = w;
+        }
+        if (ln.pos + 1 == rg.R) uncounted = D - r;
+    }
+    const uint32_t x = shift_in<false, P>(last, first, ln, 0u);
     uint32_t side[D];
     side_words<D, P>(q0, x, side);
     const Vec<D> qm = prepv<KIND, D>(in.om);
@@ -91,9 +110,9 @@ __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const Swee
         qzm = prepv<KIND, D>(in.zm);
         qzp = prepv<KIND, D>(in.zp);
     }
-    const uint32_t g0 = (uint32_t)(row * rg.ncols + (uint64_t)D * ln.pos);
-    const Vec<D> nw = row_update<KIND, DIM, D, P>(in.own, q0, side, qm, qp, &qzm, &qzp, g0, a.colour, a.t, ks, lut,
-                                                  thr_up, thr_down, true, o, pre);
+    const uint32_t g0 = (uint32_t)(row * rg.ncols + ln.col0);
+    const Vec<D> nw = row_update<KIND, DIM, D, P, RAG>(in.own, q0, side, qm, qp, &qzm, &qzp, g0, a.colour, a.t, ks,
+                                                       lut, thr_up, thr_down, true, o, pre, uncounted);
     stv<D>(colour_array(a, a.colour), row * rg.Lh + cb, nw);
 }
 
@@ -111,7 +130,7 @@ __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepA
     constexpr int kCalls = KIND == KIND_ISING_ONE ? 2 : 1;  // Philox calls per word
     Words4 pre[kPre ? kCalls * D : 1];
     if constexpr (kPre) {
-        const uint32_t g0 = (uint32_t)(((uint64_t)at.z * rg.L + at.y) * rg.ncols + (uint64_t)D * ln.pos);
+        const uint32_t g0 = (uint32_t)(((uint64_t)at.z * rg.L + at.y) * rg.ncols + ln.col0);
 #pragma unroll
         for (int i = 0; i < kCalls * D; ++i) pre[i] = philox4x32_10(kCalls * g0 + i, a.colour, a.t, 0u, ks);
         __builtin_amdgcn_sched_barrier(0);
@@ -119,18 +138,24 @@ __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepA
     const Words4* const pw = kPre ? pre : nullptr;
     // the row parity is uniform across the wave: every row of a row set has
     // the parity of rem & 1
-    if (((at.y + at.z + a.colour) & 1u) == 0)
-        rows_update<KIND, DIM, D, 0>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
-    else
-        rows_update<KIND, DIM, D, 1>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
+    const bool p1 = ((at.y + at.z + a.colour) & 1u) != 0;
+    constexpr bool kRag = D > 1 && (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE);
+    if (kRag && rg.rag != 0) {
+        if (!p1) rows_update<KIND, DIM, D, 0, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
+        else rows_update<KIND, DIM, D, 1, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
+    } else {
+        if (!p1) rows_update<KIND, DIM, D, 0, false>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
+        else rows_update<KIND, DIM, D, 1, false>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
+    }
 }
 
 // Row groups of one wave at most; the row sets per plane go to nstrips, the
 // launch's to nitems, the threads per block (waves >= 1 waves of 64, at most
-// 16) to block.
-inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg)
+// 16) to block.  `ragged`: rows whose word count D does not divide are
+// accepted (Ising kinds only).
+inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg, bool ragged)
 {
-    if (waves < 1 || waves > 16 || !make_row_geom(g, 1, D, false, rg) || rg.R > 64) return false;
+    if (waves < 1 || waves > 16 || !make_row_geom(g, 1, D, false, rg, ragged) || rg.R > 64) return false;
     rg.nstrips = 2 * cdiv(g.L, 2 * rg.slots);
     rg.nitems = rg.nstrips * rg.nplanes;
     rg.block = 64u * (uint32_t)waves;

@@ -118,15 +118,17 @@ bool lut32_ok(const sl_lattice* h)
 //     with 1 word at L = 4096 (17.1 against 17.6 with 4 rows and 2 words)
 //     and 4-row strips with 2 words from 8192; coupled NE keeps 4-row strips
 //     with 2 words;
-//   - 3D: half-sweeps by independent row groups, 4 words per lane from L = 128
-//     (L = 256: 18.4 against 19.2 for the walk with 4-row strips; L = 128: 8.8
-//     against 10.6), 1 word below (L = 64: 7.5 against 8.9); spin-1/2 takes
-//     blocks of 8 waves from L = 256 (17.3 against 17.6 with 4), else 4 (L =
-//     128: 7.6 against 8.8; spin-1 at 256: 24.7 against 24.9).
+//   - 3D: half-sweeps by independent row groups with 4 words per lane (L =
+//     256: 18.4 against 19.2 for the walk with 4-row strips; L = 64: 7.4
+//     against 8.8 with 2 words and 9.8 with 1; L = 128: 7.7 against 10.0 with
+//     1), also when 4 does not divide the row (Ising rows may be ragged: L =
+//     136: 8.7 against 13.0 with 1 word; L = 200: 13.1 against 22.1; spin-1
+//     at 200: 18.2 against 25.6); spin-1/2 takes blocks of 8 waves from L =
+//     256 (17.3 against 17.6 with 4), else 4 (L = 128: 7.7 against 8.6;
+//     spin-1 at 256: 24.7 against 24.9).
 // A fused 3D sweep would recompute a halo in two directions, so 3D uses
-// half-sweeps.  Other widths are tried in order when D does not divide the
-// row, and shapes the whole-row kernels cannot take fall back to the window
-// kernels.
+// half-sweeps.  Other widths are tried in order when a row does not fit, and
+// shapes the whole-row kernels cannot take fall back to the window kernels.
 constexpr uint64_t kResidentAuto = 16 * 1024;
 
 sl_launch auto_launch(const sl_lattice* h)
@@ -148,7 +150,7 @@ sl_launch auto_launch(const sl_lattice* h)
     const bool half_spin = h->kind == KIND_ISING_HALF;
     sl_launch l{};
     if (h->params.dim == 3) {
-        const int Ds[3] = {L >= 128 ? 4 : 1, 2, L >= 128 ? 1 : 4};
+        const int Ds[3] = {4, 2, 1};
         const int waves = L >= 256 && half_spin ? 8 : 4;
         for (int D : Ds)
             if (rows_supported(g, h->kind, waves, D, lut32_ok(h))) {

@@ -87,9 +87,19 @@ def expected_supported(sp: S.Params, launch) -> bool:
         if H < 0 or H > 16:
             return False
         ncols = sp.L // 8
+
+        def fits(d):
+            # one wave per row group; Ising rows may be ragged: the last lane
+            # of at least two holds the row's last d words
+            if d not in (1, 2, 4):
+                return False
+            if ncols % d == 0:
+                return ncols // d <= 64
+            return sp.model == S.ISING and 2 <= -(-ncols // d) <= 64
+
         if D == 0:
-            D = next((d for d in (4, 2, 1) if ncols % d == 0 and ncols // d <= 64), 4)
-        return D in (1, 2, 4) and ncols % D == 0 and ncols // D <= 64
+            D = next((d for d in (4, 2, 1) if fits(d)), 4)
+        return fits(D)
     if mode in (S.MODE_HALF_WINDOW, S.MODE_FUSED_WINDOW):
         if sp.model == S.NE_COUPLED:
             return False

@@ -24,7 +24,9 @@ def _mixed_jobs():
         S.Params(model=S.NORTH_EAST, L=128, c=0.1, seed=10),
         S.Params(L=936, T=2.3, seed=11),                   # 117-word rows: window kernel
         S.Params(L=64, T=0.05, seed=12),                   # zero thresholds: window kernel
-        S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),
+        S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),     # 5-word rows: 2 words per lane, ragged
+        S.Params(dim=3, L=56, T=4.4, seed=14),              # 7-word rows: 4 words per lane, ragged
+        S.Params(dim=3, L=72, T=4.6, h=0.05, seed=15),      # 9-word rows: 2 words per lane, ragged
     ]
     return jobs
 

@@ -82,6 +82,40 @@ def test_ising3d_shapes(L, two_s, launch):
     _check(sp, 12, launch=launch)
 
 
+# Ragged row groups: colour rows of L/8 words that 2 or 4 words per lane do
+# not divide (L % 16 = 8 or L % 32 in {8, 16, 24}); the last lane holds the
+# row's last D words, some of which lane R-2 also holds.  Row groups of 2 to
+# 33 lanes, the duplicated words in both lane orders (row parity 0 and 1).
+RAGGED_3D = [24, 40, 56, 72, 88, 120, 136]
+RAGGED_2D = [24, 40, 72, 200, 1032]
+RAGGED_LAUNCH = [(S.MODE_HALF_ROWS, 4, 2), (S.MODE_HALF_ROWS, 4, 4), (S.MODE_HALF_ROWS, 8, 4),
+                 (S.MODE_HALF_ROWS, 1, 2), (S.MODE_HALF_ROWS, 0, 0), AUTO]
+
+
+@pytest.mark.parametrize("L", RAGGED_3D)
+@pytest.mark.parametrize("two_s", [1, 2])
+@pytest.mark.parametrize("launch", RAGGED_LAUNCH)
+def test_ising3d_ragged_rows(L, two_s, launch):
+    sp = S.Params(dim=3, L=L, two_s=two_s, T=4.4 if two_s == 1 else 3.1, h=0.03 * (L % 3),
+                  seed=300 + L, record_capacity=64)
+    _check(sp, 9, launch=launch)
+
+
+@pytest.mark.parametrize("L", RAGGED_2D)
+@pytest.mark.parametrize("two_s", [1, 2])
+@pytest.mark.parametrize("launch", RAGGED_LAUNCH)
+def test_ising2d_ragged_rows(L, two_s, launch):
+    sp = S.Params(L=L, two_s=two_s, T=2.2 if two_s == 1 else 1.6, seed=400 + L, record_capacity=64)
+    _check(sp, 15, launch=launch)
+
+
+def test_ragged_rows_refused_for_ne():
+    """NE lattices keep rows that the words per lane divide."""
+    for launch in ((S.MODE_HALF_ROWS, 4, 2), (S.MODE_HALF_ROWS, 4, 4)):
+        assert_refused(S.Params(model=S.NORTH_EAST, L=40, c=0.2, seed=1), launch)
+        assert_refused(S.Params(model=S.NE_COUPLED, L=40, J=1.0, T=2.0, c=0.3, seed=1), launch)
+
+
 @pytest.mark.parametrize("L", [8, 32, 72, 1040, 2048])
 @pytest.mark.parametrize("c", [0.05, 0.2, 0.6])
 @pytest.mark.parametrize("launch", [SIMPLE, HALF_W, FUSED_W, RESIDENT, AUTO] + ROW)
