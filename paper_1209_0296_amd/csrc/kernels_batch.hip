@@ -264,11 +264,11 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHo
         RowGeom rg;
         if (g.dim == 3) {
             // row groups without a walk (3D jobs are Ising): the widest D that
-            // divides the row, else a ragged row of two or four words per lane
-            // with the fewer duplicated words (four on a tie), else one word
-            const uint32_t nc = g.Lh / 4;
-            const int rag_d = cdiv(nc, 4) * 4 <= cdiv(nc, 2) * 2 ? 4 : 2;
-            const int order[5] = {4, 2, rag_d, 6 - rag_d, 1};
+            // divides the row, else a ragged row of four words per lane, then
+            // of two (single lattices with ragged rows: four words per lane
+            // beat two even with more duplicated words, L = 136 and 200), else
+            // one word
+            const int order[5] = {4, 2, 4, 2, 1};
             for (int i = 0; i < 5; ++i) {
                 const int D = order[i];
                 if (!make_rows_geom(g, D, 4, rg, i == 2 || i == 3)) continue;
