@@ -263,15 +263,12 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHo
     if (lut32_ok) {
         RowGeom rg;
         if (g.dim == 3) {
-            // row groups without a walk (3D jobs are Ising): the widest D that
-            // divides the row, else a ragged row of four words per lane, then
-            // of two (single lattices with ragged rows: four words per lane
-            // beat two even with more duplicated words, L = 136 and 200), else
-            // one word
-            const int order[5] = {4, 2, 4, 2, 1};
-            for (int i = 0; i < 5; ++i) {
-                const int D = order[i];
-                if (!make_rows_geom(g, D, 4, rg, i == 2 || i == 3)) continue;
+            // row groups without a walk (3D jobs are Ising): four words per
+            // lane, ragged where four do not divide the row, else two, else
+            // one (on single lattices four ragged words per lane beat two
+            // exact ones: L = 208, 13.2 against 16.1 us per sweep)
+            for (int D : {4, 2, 1}) {
+                if (!make_rows_geom(g, D, 4, rg, true)) continue;
                 __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
                 out.variant = D == 4 ? kBvRowsD4 : D == 2 ? kBvRowsD2 : kBvRowsD1;
                 out.nitems = rg.nitems;
