@@ -563,8 +563,9 @@ sl_status sl_batch_sweep(sl_batch* b, uint64_t n)
     ++b->calls;
 
     // the row-group families get a stream of their own when another family runs
-    const bool rows_work = count[1] || count[3], other_work = count[0] || count[2];
-    const bool split = rows_work && other_work;
+    bool par_work = false, main_work = false;
+    for (int f = 0; f < kBatchFamilies; ++f) (row_family(f) ? par_work : main_work) |= count[f] != 0;
+    const bool split = par_work && main_work;
     if (nres || split) {
         e = hipEventRecord(b->ev_fork, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch: fork");
