@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict_
 
 }  // namespace
 
-bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHost& out)
+bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, bool ising, RowGeomHost& out)
 {
     out = RowGeomHost{};
     static_assert(sizeof(RowGeom) <= sizeof(out.bytes), "RowGeom storage");
@@ -268,7 +268,7 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHo
             // one (on single lattices four ragged words per lane beat two
             // exact ones: L = 208, 13.2 against 16.1 us per sweep)
             for (int D : {4, 2, 1}) {
-                if (!make_rows_geom(g, D, 4, rg, true)) continue;
+                if (!make_rows_geom(g, D, 4, rg, ising)) continue;
                 __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
                 out.variant = D == 4 ? kBvRowsD4 : D == 2 ? kBvRowsD2 : kBvRowsD1;
                 out.nitems = rg.nitems;
@@ -276,7 +276,10 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHo
                 return true;
             }
         } else if (allow_fused) {
-            // two or one words per lane (colour rows up to L = 1024)
+            // two or one words per lane (colour rows up to L = 1024).  Measured
+            // and dropped: two ragged words per lane for Ising rows of an odd
+            // word count above 64 (the served stream lost 5% against the
+            // column windows)
             for (int D : {2, 1}) {
                 if (!make_row_geom(g, H, D, true, rg) || rg.R > 64) continue;
                 __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));

@@ -147,6 +147,35 @@ __device__ __forceinline__ void side_words(const Vec<D>& o, uint32_t x, uint32_t
     }
 }
 
+// Edge words a lane passes to its neighbours for shift_in, and how many of
+// its first words another lane also holds and counts.  Ragged rows (RAG):
+// ncols = (R - 1) D + rag and the last lane holds words ncols - D .. ncols - 1,
+// so its first D - rag words are also lane R-2's last ones.  Both copies of
+// such a word see the same neighbours and random numbers, so they store the
+// same value; only lane R-2's copy is counted.  For that, for p = 0 lane R-2
+// passes word rag - 1 (the one before the last lane's first word), for p = 1
+// the last lane passes word D - rag (the one after lane R-2's last word).
+template <int D, int P, bool RAG>
+__device__ __forceinline__ uint32_t edge_words(const Vec<D>& q, const RowGeom& rg, const Lanes& ln, uint32_t& last,
+                                               uint32_t& first)
+{
+    last = q.w[D - 1];
+    first = q.w[0];
+    if constexpr (RAG) {
+        static_assert(D > 1, "one word per lane divides every row");
+        const uint32_t r = rg.rag;  // 1 .. D-1, wave-uniform
+        if constexpr (P == 0) {
+            const uint32_t w = D == 2 ? q.w[0] : (r == 1 ? q.w[0] : r == 2 ? q.w[1 % D] : q.w[2 % D]);
+            if (ln.pos + 2 == rg.R) last = w;
+        } else {
+            const uint32_t w = D == 2 ? q.w[1 % D] : (r == 1 ? q.w[3 % D] : r == 2 ? q.w[2 % D] : q.w[1 % D]);
+            if (ln.pos + 1 == rg.R) first = w;
+        }
+        return ln.pos + 1 == rg.R ? D - r : 0u;
+    }
+    return 0u;
+}
+
 // ---- tables ---------------------------------------------------------------
 struct RowLuts {
     uint64_t e[3 * 2 * 13];  // spin-1 entries; spin-1/2 uses the first words as u32

@@ -72,13 +72,7 @@ __device__ __forceinline__ void rows_load(RowsIn<DIM, D>& in, const SweepArgs& a
     }
 }
 
-// Ragged rows (RAG): ncols = (R - 1) D + rag, and the last lane holds words
-// ncols - D .. ncols - 1, so its first D - rag words are also lane R-2's last
-// ones.  Both copies of such a word see the same neighbours and random
-// numbers, so they store the same value; only lane R-2's copy is counted.  The
-// edge words the lanes pass on change to keep that true: for p = 0 lane R-2
-// passes word rag - 1 (the one before the last lane's first word), for p = 1
-// the last lane passes word D - rag (the one after lane R-2's last word).
+// RAG: a ragged row (edge_words).
 template <int KIND, int DIM, int D, int P, bool RAG>
 __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
                                             const RowsAt& at, const Lanes& ln, const PhiloxKey& ks,
@@ -88,18 +82,8 @@ __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const Swee
     const uint64_t row = (uint64_t)at.z * rg.L + at.y;
     const uint64_t cb = 4ull * ln.col0;
     const Vec<D> q0 = prepv<KIND, D>(in.o0);
-    uint32_t last = q0.w[D - 1], first = q0.w[0], uncounted = 0;
-    if constexpr (RAG) {
-        const uint32_t r = rg.rag;  // 1 .. D-1, wave-uniform
-        if constexpr (P == 0) {
-            const uint32_t w = D == 2 ? q0.w[0] : (r == 1 ? q0.w[0] : r == 2 ? q0.w[1 % D] : q0.w[2 % D]);
-            if (ln.pos + 2 == rg.R) last = w;
-        } else {
-            const uint32_t w = D == 2 ? q0.w[1 % D] : (r == 1 ? q0.w[3 % D] : r == 2 ? q0.w[2 % D] : q0.w[1 % D]);
-            if (ln.pos + 1 == rg.R) first = w;
-        }
-        if (ln.pos + 1 == rg.R) uncounted = D - r;
-    }
+    uint32_t last, first;
+    const uint32_t uncounted = edge_words<D, P, RAG>(q0, rg, ln, last, first);
     const uint32_t x = shift_in<false, P>(last, first, ln, 0u);
     uint32_t side[D];
     side_words<D, P>(q0, x, side);

@@ -23,6 +23,8 @@ def _mixed_jobs():
         S.Params(model=S.NORTH_EAST, L=72, c=0.2, seed=9),
         S.Params(model=S.NORTH_EAST, L=128, c=0.1, seed=10),
         S.Params(L=936, T=2.3, seed=11),                   # 117-word rows: window kernel
+        S.Params(L=600, two_s=2, T=1.6, seed=16),          # 75-word rows: window kernel, spin-1
+        S.Params(model=S.NORTH_EAST, L=936, c=0.2, seed=17),  # NE, 117-word rows: window kernel
         S.Params(L=64, T=0.05, seed=12),                   # zero thresholds: window kernel
         S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),     # 5-word rows: 4 words per lane, ragged
         S.Params(dim=3, L=56, T=4.4, seed=14),              # 7-word rows: 4 words per lane, ragged
@@ -47,7 +49,7 @@ def test_mixed_batch_matches_each_job_alone(flags):
     without graph replay."""
     print(f"case mixed batch flags={flags}", flush=True)
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=64, flags=flags)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=24, record_capacity=64, flags=flags)
     ids = [b.add(p, sweeps=12) for p in jobs]
     assert all(i is not None for i in ids)
     recs = {i: [S.records_to_array(b.measure(i))] for i in ids}
@@ -159,7 +161,7 @@ def test_drain_collects_every_job(flags):
     chunks of 7 sweeps flip the fused jobs' current copy every call."""
     print(f"case drain flags={flags}", flush=True)
     jobs = _mixed_jobs()
-    b = S.Batch(arena_bytes=96 << 20, max_jobs=16, record_capacity=8, flags=flags)
+    b = S.Batch(arena_bytes=96 << 20, max_jobs=24, record_capacity=8, flags=flags)
     ids = [b.add(p, sweeps=10 + k) for k, p in enumerate(jobs)]
     recs = {i: [] for i in ids}
     while True:
@@ -231,7 +233,7 @@ def test_graph_cache_eviction_keeps_results():
     jobs = [S.Params(dim=3, L=32, T=4.5, seed=401),              # row groups, spin-1/2
             S.Params(dim=3, L=40, two_s=2, T=3.0, seed=402),     # row groups, spin-1
             S.Params(L=512, T=2.3, seed=403),                    # fused
-            S.Params(L=936, T=2.2, seed=404),                    # column windows
+            S.Params(model=S.NORTH_EAST, L=936, c=0.3, seed=404),  # column windows
             S.Params(L=64, T=2.0, seed=405)]                     # resident
     total = sum(range(1, 25))
     b = S.Batch(arena_bytes=96 << 20, max_jobs=8, record_capacity=32)
