@@ -100,7 +100,11 @@ __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const Swee
     stv<D>(colour_array(a, a.colour), row * rg.Lh + cb, nw);
 }
 
-template <int KIND, int DIM, int D>
+// Ragged-row handling of a kernel: none, every row (rg.rag != 0), or chosen
+// per launch argument (batched jobs of both kinds share a kernel).
+enum RagMode { kRagNone = 0, kRagAll = 1, kRagRuntime = 2 };
+
+template <int KIND, int DIM, int D, int RAGS>
 __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
                                           const RowsAt& at, const Lanes& ln, const PhiloxKey& ks, const RowLuts& lut,
                                           uint64_t thr_up, uint64_t thr_down, Obs& o)
@@ -123,8 +127,8 @@ __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepA
     // the row parity is uniform across the wave: every row of a row set has
     // the parity of rem & 1
     const bool p1 = ((at.y + at.z + a.colour) & 1u) != 0;
-    constexpr bool kRag = D > 1 && (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE);
-    if (kRag && rg.rag != 0) {
+    constexpr bool kRag = D > 1 && (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE) && RAGS != kRagNone;
+    if (kRag && (RAGS == kRagAll || rg.rag != 0)) {
         if (!p1) rows_update<KIND, DIM, D, 0, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
         else rows_update<KIND, DIM, D, 1, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
     } else {
@@ -149,7 +153,7 @@ inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg, bool ra
 
 // Row sets it0 .. it0 + K - 1 of one wave (it0 wave-uniform, K = 4 / D).  Every thread of
 // the block calls this: the table build inside ends in a workgroup barrier.
-template <int KIND, int DIM, int D>
+template <int KIND, int DIM, int D, int RAGS = kRagRuntime>
 __device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, uint32_t it0, const Lanes& ln,
                                          const uint64_t* table, RowLuts& lut, Obs& o)
 {
@@ -168,8 +172,8 @@ __device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, 
             RowsIn<DIM, D> in0, in1;
             rows_load<DIM, D>(in0, a, rg, at0, ln);
             rows_load<DIM, D>(in1, a, rg, at1, ln);
-            rows_step<KIND, DIM, D>(in0, a, rg, at0, ln, ks, lut, thr_up, thr_down, o);
-            rows_step<KIND, DIM, D>(in1, a, rg, at1, ln, ks, lut, thr_up, thr_down, o);
+            rows_step<KIND, DIM, D, RAGS>(in0, a, rg, at0, ln, ks, lut, thr_up, thr_down, o);
+            rows_step<KIND, DIM, D, RAGS>(in1, a, rg, at1, ln, ks, lut, thr_up, thr_down, o);
         }
     } else {
 #pragma nounroll
@@ -177,7 +181,7 @@ __device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, 
             const RowsAt at = rows_at(rg, it0 + k, ln.slot);
             RowsIn<DIM, D> in;
             rows_load<DIM, D>(in, a, rg, at, ln);
-            rows_step<KIND, DIM, D>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
+            rows_step<KIND, DIM, D, RAGS>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o);
         }
     }
 }
