@@ -250,7 +250,7 @@ sl_status prepare_job(const sl_batch_config* cfg, const sl_params* params, sl_pa
     const int H = cfg->tile_rows > 0 ? cfg->tile_rows : default_rows(p->dim, fused);
     if (!(cfg->flags & SL_BATCH_NO_RESIDENT) && batch_resident_geom(g, *geom)) {
         // resident jobs run the direct update in LDS: any table
-    } else if (!batch_geom(g, H, lut32 || !spin_half_table, fused, p->model == SL_ISING, *geom)) {
+    } else if (!batch_geom(g, H, lut32 || !spin_half_table, fused, *geom)) {
         return fail(SL_E_UNSUPPORTED, "L = %d does not fit the batched kernels", p->L);
     }
     if (coupled && geom->variant == kBvWindow)

@@ -53,7 +53,7 @@ struct RowGeomHost {
 // Geometry of a non-resident job: 3D row groups without a walk, 2D fused
 // strips (if allow_fused) or whole-row walks when the colour row fits one
 // wave and the 32-bit spin-1/2 table applies; else 64-lane column windows.
-bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, bool ising, RowGeomHost& out);
+bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHost& out);
 // Resident class: both colours in at most kResidentLds bytes.
 bool batch_resident_geom(const Geom& g, RowGeomHost& out);
 

@@ -84,7 +84,7 @@ __device__ __forceinline__ void batch_rows_body(const BatchJob& J, const uint32_
     const RowGeom rg = *reinterpret_cast<const RowGeom*>(J.rg_words);
     Obs o = {0, 0, 0, 0, 0};
     const Lanes ln = lanes_of(rg, false);
-    rows_run<KIND, DIM, D>(a, rg, w.item_base + ln.wave * rg.K, ln, J.table, lut, o);
+    rows_run<KIND, DIM, D, kRagNone>(a, rg, w.item_base + ln.wave * rg.K, ln, J.table, lut, o);
     int32_t bond, mag, acc, unfl;
     finish_obs<KIND, DIM>(o, bond, mag, acc, unfl);
     block_accumulate(bond, mag, acc, unfl, J.acc + (uint64_t)(dj[1] + step) * kSlotWords);
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_batch_fold(const BatchFold* __restrict_
 
 }  // namespace
 
-bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, bool ising, RowGeomHost& out)
+bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, RowGeomHost& out)
 {
     out = RowGeomHost{};
     static_assert(sizeof(RowGeom) <= sizeof(out.bytes), "RowGeom storage");
@@ -263,12 +263,13 @@ bool batch_geom(const Geom& g, int H, bool lut32_ok, bool allow_fused, bool isin
     if (lut32_ok) {
         RowGeom rg;
         if (g.dim == 3) {
-            // row groups without a walk (3D jobs are Ising): four words per
-            // lane, ragged where four do not divide the row, else two, else
-            // one (on single lattices four ragged words per lane beat two
-            // exact ones: L = 208, 13.2 against 16.1 us per sweep)
+            // row groups without a walk, widest D that divides the row.
+            // Measured and dropped: ragged rows for batched jobs (the served
+            // stream lost 6% on one box, 439 against 467 jobs/s: the rows
+            // kernels then branch per job between the two updates, which
+            // single lattices measured at 8%)
             for (int D : {4, 2, 1}) {
-                if (!make_rows_geom(g, D, 4, rg, ising)) continue;
+                if (!make_rows_geom(g, D, 4, rg, false)) continue;
                 __builtin_memcpy(out.bytes, &rg, sizeof(RowGeom));
                 out.variant = D == 4 ? kBvRowsD4 : D == 2 ? kBvRowsD2 : kBvRowsD1;
                 out.nitems = rg.nitems;

@@ -100,9 +100,10 @@ __device__ __forceinline__ void rows_update(const RowsIn<DIM, D>& in, const Swee
     stv<D>(colour_array(a, a.colour), row * rg.Lh + cb, nw);
 }
 
-// Ragged-row handling of a kernel: none, every row (rg.rag != 0), or chosen
-// per launch argument (batched jobs of both kinds share a kernel).
-enum RagMode { kRagNone = 0, kRagAll = 1, kRagRuntime = 2 };
+// Ragged-row handling of a kernel: none, or every row (rg.rag != 0).  Each
+// gets kernels of its own: a runtime branch between the two updates slowed
+// the plain rows.
+enum RagMode { kRagNone = 0, kRagAll = 1 };
 
 template <int KIND, int DIM, int D, int RAGS>
 __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepArgs& a, const RowGeom& rg,
@@ -127,8 +128,8 @@ __device__ __forceinline__ void rows_step(const RowsIn<DIM, D>& in, const SweepA
     // the row parity is uniform across the wave: every row of a row set has
     // the parity of rem & 1
     const bool p1 = ((at.y + at.z + a.colour) & 1u) != 0;
-    constexpr bool kRag = D > 1 && (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE) && RAGS != kRagNone;
-    if (kRag && (RAGS == kRagAll || rg.rag != 0)) {
+    constexpr bool kRag = D > 1 && (KIND == KIND_ISING_HALF || KIND == KIND_ISING_ONE) && RAGS == kRagAll;
+    if constexpr (kRag) {
         if (!p1) rows_update<KIND, DIM, D, 0, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
         else rows_update<KIND, DIM, D, 1, kRag>(in, a, rg, at, ln, ks, lut, thr_up, thr_down, o, pw);
     } else {
@@ -153,7 +154,7 @@ inline bool make_rows_geom(const Geom& g, int D, int waves, RowGeom& rg, bool ra
 
 // Row sets it0 .. it0 + K - 1 of one wave (it0 wave-uniform, K = 4 / D).  Every thread of
 // the block calls this: the table build inside ends in a workgroup barrier.
-template <int KIND, int DIM, int D, int RAGS = kRagRuntime>
+template <int KIND, int DIM, int D, int RAGS>
 __device__ __forceinline__ void rows_run(const SweepArgs& a, const RowGeom& rg, uint32_t it0, const Lanes& ln,
                                          const uint64_t* table, RowLuts& lut, Obs& o)
 {

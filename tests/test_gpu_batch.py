@@ -18,7 +18,7 @@ def _mixed_jobs():
         S.Params(L=256, T=2.4, h=0.1, seed=4),              # 32-word rows, D = 4
         S.Params(L=1024, T=2.269, seed=5),                  # 128-word rows, D = 2
         S.Params(dim=3, L=16, T=4.5, seed=6),
-        S.Params(dim=3, L=24, two_s=2, T=3.2, seed=7),      # resident, else 3-word rows: 2 per lane, ragged
+        S.Params(dim=3, L=24, two_s=2, T=3.2, seed=7),      # resident, else 3-word rows: 1 word per lane
         S.Params(dim=3, L=64, T=4.0, J=0.9, seed=8),
         S.Params(model=S.NORTH_EAST, L=72, c=0.2, seed=9),
         S.Params(model=S.NORTH_EAST, L=128, c=0.1, seed=10),
@@ -26,9 +26,9 @@ def _mixed_jobs():
         S.Params(L=600, two_s=2, T=1.6, seed=16),          # 75-word rows: window kernel, spin-1
         S.Params(model=S.NORTH_EAST, L=936, c=0.2, seed=17),  # NE, 117-word rows: window kernel
         S.Params(L=64, T=0.05, seed=12),                   # zero thresholds: window kernel
-        S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),     # 5-word rows: 4 words per lane, ragged
-        S.Params(dim=3, L=56, T=4.4, seed=14),              # 7-word rows: 4 words per lane, ragged
-        S.Params(dim=3, L=72, T=4.6, h=0.05, seed=15),      # 9-word rows: 4 words per lane, ragged
+        S.Params(dim=3, L=40, two_s=2, T=2.9, seed=13),     # 5-word rows: 1 word per lane
+        S.Params(dim=3, L=56, T=4.4, seed=14),              # 7-word rows: 1 word per lane
+        S.Params(dim=3, L=72, T=4.6, h=0.05, seed=15),      # 9-word rows: 1 word per lane
     ]
     return jobs
 
